@@ -446,3 +446,55 @@ def test_ig_decreases_toward_object(oracle_lib):
     ig, _ = oracle.eval_viewpoints(s, cam, look_at(pos, cen))
     assert np.all(np.diff(ig) <= 1e-3 * ig[:-1])
     assert ig[-1] < 0.6 * ig[0]
+
+
+# ------------------------------------------------ P8: trajectory union -----
+
+def _traj_scene():
+    sc = scene_spheres(n=40, voxel=0.1, n_spheres=15, seed=21)
+    cam = Camera(10, 8, 60, 45, 1.8)
+    return sc, cam
+
+
+def test_trajectory_union_matches_distinct_voxels(oracle_lib):
+    """|U| and the class counts equal those of the distinct voxels over the full ray
+    paths of all poses; visits equal the summed per-perspective steps."""
+    from workloads import trajectories_walk
+    sc, cam = _traj_scene()
+    traj = trajectories_walk(sc.poi, 3, 4, seed=22)
+    ig, counts, visits = oracle.eval_trajectories(sc, cam, traj)
+    flatP = sc.P.ravel()
+    for t in range(traj.shape[0]):
+        seen = set()
+        per_pose = []
+        for l in range(traj.shape[1]):
+            mine = set()
+            for j in range(cam.height):
+                for i in range(cam.width):
+                    mine.update(int(v) for v in oracle.cast_ray(sc, cam, traj[t, l], i, j)["path"])
+            per_pose.append(len(mine))
+            seen |= mine
+        vals = flatP[np.array(sorted(seen))]
+        assert counts[t, 0] == len(seen)
+        assert counts[t, 1] == np.count_nonzero(vals > 0.5)
+        assert counts[t, 2] == np.count_nonzero(vals < 0.5)
+        assert counts[t, 3] == np.count_nonzero(vals == 0.5)
+        assert counts[t, 0] <= sum(per_pose)
+        g = np.where(vals > 0.5, np.float32(1) - vals, np.where(vals < 0.5, vals, np.float32(1)))
+        assert ig[t] == pytest.approx(float(np.sum(g.astype(np.float64))), rel=1e-7)
+        _, st = oracle.eval_viewpoints(sc, cam, traj[t])
+        assert visits[t] == st.sum()
+
+
+def test_trajectory_duplicate_and_permutation_invariance(oracle_lib):
+    from workloads import trajectories_walk
+    sc, cam = _traj_scene()
+    traj = trajectories_walk(sc.poi, 2, 5, seed=23)
+    ig, counts, visits = oracle.eval_trajectories(sc, cam, traj)
+    perm = traj[:, [4, 2, 0, 3, 1]]
+    ig2, counts2, _ = oracle.eval_trajectories(sc, cam, perm)
+    assert np.array_equal(counts, counts2) and np.array_equal(ig, ig2)
+    dup = np.concatenate([traj, traj[:, :2]], axis=1)
+    ig3, counts3, visits3 = oracle.eval_trajectories(sc, cam, dup)
+    assert np.array_equal(counts, counts3) and np.array_equal(ig, ig3)
+    assert np.all(visits3 > visits)
