@@ -1,0 +1,196 @@
+/*
+ * nbt_ig.h -- C ABI of the MI355X (gfx950) information-gain raycasting library.
+ *
+ * The library evaluates the information gain (IG) that camera perspectives
+ * around a point of interest would collect from a voxel occupancy map, as
+ * defined in Sec. III of Renz et al., "Next-Best-Trajectory Planning of Robot
+ * Manipulators for Effective Observation and Exploration" (2025):
+ *
+ *   - every perspective casts N_E = width*height rays from its centre to a
+ *     grid of endpoints on the far frustum plane at depth d_Cam, bounded by
+ *     the border rays at d_h = d_Cam tan(FoV_h/2), d_v = d_Cam tan(FoV_v/2)
+ *     (Sec. III, endpoint calculation);
+ *   - a ray's gain is the sum of the voxel gains g(v) (Eq. 2: 1-P occupied,
+ *     P free, 1 unknown) over the voxels it meets, up to and including the
+ *     first occupied voxel or up to its endpoint (Sec. III, IG calculation);
+ *   - a perspective's IG is the mean ray gain over its N_E rays.
+ *
+ * Conventions the paper leaves open (all arithmetic in IEEE binary32 without
+ * fused multiply-add, gains accumulated in binary64):
+ *   - ray k = j*width + i; endpoint (u, v, d_Cam) in camera coordinates with
+ *     u = d_h*((2i-(width-1))/(width-1)) (0 when width == 1), likewise v;
+ *   - pose = 12 floats: row-major 3x3 camera->world rotation R (columns:
+ *     camera x = image right, y = image down, z = viewing direction), then
+ *     the centre t; world endpoint e = t + ((R_a0*u + R_a1*v) + R_a2*d_Cam);
+ *   - the segment t -> e is walked voxel by voxel (Amanatides-Woo 3D-DDA) in
+ *     voxel units (x - origin) * (1/voxel_size), clipped to the map and to
+ *     the segment; ties between axes advance x before y before z; a face
+ *     crossing exactly at the endpoint is still taken; voxels outside the
+ *     map do not exist (pad the map with P = 0.5 to treat them as unknown);
+ *   - a ray whose voxel-unit coordinates are not finite is INVALID and makes
+ *     its perspective's IG NaN.
+ *   - voxel (ix,iy,iz) spans origin + voxel_size*[i, i+1); its linear index
+ *     is (iz*ny + iy)*nx + ix whatever the internal layout.
+ *
+ * Memory: unless stated otherwise every pointer argument is a caller-owned
+ * DEVICE pointer (e.g. a torch tensor's data_ptr()).  Calls are enqueued on
+ * `stream` (a hipStream_t; NULL = the default stream) and return before the
+ * work completes.  Calls that use the same context must be ordered on one
+ * stream: they share the context's reduction workspace.
+ *
+ * Errors: every entry point returns an nbt_ig_status; nothing throws or
+ * aborts across the ABI.  Argument errors are reported before anything is
+ * launched (NBT_IG_EINVAL) and nbt_ig_last_error() returns a thread-local
+ * message for the last failure.  Faults inside kernels surface as
+ * NBT_IG_EDEVICE from a later call that synchronises.
+ */
+#ifndef NBT_IG_H
+#define NBT_IG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NBT_IG_ABI_VERSION 1
+
+typedef enum {
+    NBT_IG_OK = 0,
+    NBT_IG_EINVAL = -1,         /* invalid argument; nothing was launched */
+    NBT_IG_ENOMEM = -2,         /* device or host allocation failed */
+    NBT_IG_EDEVICE = -3,        /* a HIP runtime call or a kernel failed */
+    NBT_IG_EUNSUPPORTED = -4    /* size or device outside what this build supports */
+} nbt_ig_status;
+
+/* Why a ray stopped (nbt_ig_ray_digest.reason). */
+enum {
+    NBT_IG_RAY_MISS = 0,        /* the segment never enters the map */
+    NBT_IG_RAY_HIT = 1,         /* stopped at (and including) its first occupied voxel */
+    NBT_IG_RAY_END = 2,         /* reached its endpoint inside the map */
+    NBT_IG_RAY_EXIT = 3,        /* left the map before its endpoint */
+    NBT_IG_RAY_INVALID = 4      /* non-finite coordinates */
+};
+
+/* Voxel states (Eq. 2). */
+enum { NBT_IG_OCCUPIED = 1, NBT_IG_FREE = 2, NBT_IG_UNKNOWN = 3 };
+
+typedef struct nbt_ig_ctx nbt_ig_ctx;
+typedef struct nbt_ig_map nbt_ig_map;
+
+/* The far-plane endpoint grid of one perspective (Sec. III, endpoint calculation). */
+typedef struct {
+    uint32_t width, height;     /* endpoints per row / column, each >= 1; N_E = width*height */
+    float tan_half_fov_h;       /* tan(FoV_h/2), > 0, rounded once from double on the host */
+    float tan_half_fov_v;       /* tan(FoV_v/2), > 0 */
+    float range;                /* d_Cam: far-plane depth along the camera z axis, metres, > 0 */
+} nbt_ig_camera;
+
+/* Voxel classification from occupancy probability (Eq. 2 states). */
+typedef struct {
+    float occ_threshold;        /* Occupied if P > occ_threshold (default 0.5) */
+    float free_threshold;       /* Free if P < free_threshold (default 0.5); Unknown otherwise */
+} nbt_ig_classify;
+
+/* Per-ray record of the parity mode (32 bytes). */
+typedef struct {
+    uint64_t hash;              /* FNV-1a-64 over the visited linear indices, 4 little-endian bytes each */
+    double gain;                /* g_R: summed Eq. 2 gains of the visited voxels */
+    uint32_t steps;             /* voxels visited (N_O) */
+    int32_t stop_lin;           /* linear index of the last visited voxel, -1 if none */
+    uint32_t reason;            /* NBT_IG_RAY_* */
+    uint32_t reserved;
+} nbt_ig_ray_digest;
+
+/* ---- context ---------------------------------------------------------------
+ * A context binds one device (HIP ordinal) and owns the reduction workspace.
+ * Fails with NBT_IG_EUNSUPPORTED when the device is not gfx950.
+ */
+int nbt_ig_ctx_create(int device, nbt_ig_ctx** out);
+void nbt_ig_ctx_destroy(nbt_ig_ctx* ctx);       /* NULL is a no-op; caller syncs its streams first */
+
+/* ---- maps -------------------------------------------------------------------
+ * Copies the occupancy grid `prob` (float32 [nz][ny][nx], x fastest, values
+ * in [0,1]; HOST or DEVICE pointer) into a device-resident encoded map: each
+ * voxel stores its Eq. 2 gain with the sign bit marking Occupied, inside a
+ * one-voxel border that stops every ray leaving the map.  1 <= n <= 4096 per
+ * axis and (nx+2)(ny+2)(nz+2) < 2^30.  `origin` (HOST, 3 floats) is the world
+ * position of the min corner of voxel (0,0,0); `voxel_size` > 0 is s_Vox.
+ * `cls` may be NULL (0.5/0.5); 0 <= free_threshold <= occ_threshold <= 1.
+ * Probabilities outside [0,1] or NaN give NBT_IG_EINVAL (checked on the
+ * device; the call synchronises `stream` once).  The map is immutable and
+ * may be read by concurrent evaluations; destroy it only after they finish.
+ */
+int nbt_ig_create_map(nbt_ig_ctx* ctx, const float* prob, int nx, int ny, int nz, float voxel_size,
+                      const float origin[3], const nbt_ig_classify* cls, void* stream,
+                      nbt_ig_map** out);
+void nbt_ig_destroy_map(nbt_ig_map* map);        /* NULL is a no-op */
+
+/* Dimensions of a map (HOST outputs, any may be NULL). */
+int nbt_ig_map_info(const nbt_ig_map* map, int* nx, int* ny, int* nz, float* voxel_size,
+                    float origin[3], size_t* device_bytes);
+
+/* ---- per-perspective IG (Sec. III, IG calculation) ----------------------------
+ * ig_out[p] = g_P of pose p: the mean over its N_E rays of the ray gain g_R
+ * (Eq. 2 summed to the first occupied voxel or the endpoint), rounded once
+ * to float32; NaN if any of its rays is INVALID.  steps_out[p] (may be NULL)
+ * = total voxels visited by its rays (exact).  poses: float32 [n][12].
+ * n == 0 is a no-op.  Results are bit-identical from run to run.
+ */
+int nbt_ig_eval_viewpoints(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                           uint32_t n, float* ig_out, uint64_t* steps_out, void* stream);
+
+/* ---- parity mode ---------------------------------------------------------------
+ * One nbt_ig_ray_digest per ray: out[p*N_E + k] for pose p, ray k.
+ */
+int nbt_ig_trace_rays(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                      uint32_t n, nbt_ig_ray_digest* out, void* stream);
+
+/* Full voxel sequences of selected rays.  rays: uint32 [count][2] = (pose
+ * index, ray index k); lin_out: int32 [count][max_len] receives the visited
+ * linear indices in order (entries past the ray's length are left as is);
+ * len_out: uint32 [count] receives the full number of visited voxels (which
+ * may exceed max_len; then only the first max_len are written).  Rays whose
+ * pose index >= n or ray index >= N_E get length 0.
+ */
+int nbt_ig_trace_paths(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                       uint32_t n, const uint32_t* rays, uint32_t count, uint32_t max_len,
+                       int32_t* lin_out, uint32_t* len_out, void* stream);
+
+/* ---- launch shape (set by the autotuner) -----------------------------------------
+ * How nbt_ig_eval_viewpoints maps rays to the GPU: waves_per_group in
+ * {1,2,4,8} wavefronts per workgroup; each wave walks pixel tiles of
+ * (1<<tile_w_log2) x (64>>tile_w_log2) rays (tile_w_log2 in 0..6);
+ * tiles_per_wave >= 1 tiles per wave per workgroup; xcd_remap != 0 gives
+ * each of the 8 XCDs a contiguous range of perspectives.  Any shape gives
+ * the same step counts; IG agrees to the last-place rounding of its sum.
+ */
+typedef struct {
+    int32_t waves_per_group;
+    int32_t tile_w_log2;
+    int32_t tiles_per_wave;
+    int32_t xcd_remap;
+} nbt_ig_launch;
+
+int nbt_ig_ctx_set_launch(nbt_ig_ctx* ctx, const nbt_ig_launch* launch);
+int nbt_ig_ctx_get_launch(const nbt_ig_ctx* ctx, nbt_ig_launch* launch);
+
+/* ---- helpers ------------------------------------------------------------------- */
+
+/* Endpoint grid from the paper's grid scaling (Sec. III: endpoint spacing
+ * s_G * s_Vox on the far plane, including both border rays):
+ * width = floor(2 d_h / (s_G s_Vox)) + 1, height likewise with d_v.
+ * Angles in radians; all outputs HOST. */
+int nbt_ig_camera_from_grid(double fov_h, double fov_v, double d_cam, double s_vox, double s_g,
+                            nbt_ig_camera* out);
+
+const char* nbt_ig_status_string(int status);
+const char* nbt_ig_last_error(void);             /* thread-local; never NULL */
+int nbt_ig_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBT_IG_H */

@@ -1,0 +1,19 @@
+"""MI355X-native information-gain raycasting for Next-Best-Trajectory planning.
+
+The compute path lives in libnbt_ig.so (hand-written HIP for gfx950, C ABI in
+include/nbt_ig.h); ``binding`` marshals torch tensors into it.  Importing the
+package fails when the library has not been built.
+"""
+
+from . import binding
+from .binding import (
+    NbtError, Context, Map, CameraT, camera, camera_from_grid,
+    eval_viewpoints, trace_rays, trace_paths,
+    RAY_MISS, RAY_HIT, RAY_END, RAY_EXIT, RAY_INVALID,
+)
+
+__all__ = [
+    "binding", "NbtError", "Context", "Map", "CameraT", "camera", "camera_from_grid",
+    "eval_viewpoints", "trace_rays", "trace_paths",
+    "RAY_MISS", "RAY_HIT", "RAY_END", "RAY_EXIT", "RAY_INVALID",
+]

@@ -1,0 +1,267 @@
+"""Thin ctypes binding of libnbt_ig.so (argument marshalling only).
+
+Every function here forwards to the C ABI declared in include/nbt_ig.h with
+the same name minus the ``nbt_ig_`` prefix.  Device buffers are torch tensors
+(PyTorch-ROCm provides allocation and the current HIP stream); no
+computation of the method happens in Python.  Importing this module raises
+ImportError when the HIP library has not been built, so nothing can fall
+back to another implementation silently.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnbt_ig.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; g.build()'` "
+                      "(hipcc --offload-arch=gfx950)")
+
+_lib = C.CDLL(LIB_PATH)
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
+RAY_MISS, RAY_HIT, RAY_END, RAY_EXIT, RAY_INVALID = 0, 1, 2, 3, 4
+OCCUPIED, FREE, UNKNOWN = 1, 2, 3
+
+
+class NbtError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"[{status}] {message}")
+        self.status = status
+
+
+class CameraT(C.Structure):
+    _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("tan_half_fov_h", C.c_float),
+                ("tan_half_fov_v", C.c_float), ("range", C.c_float)]
+
+
+class LaunchT(C.Structure):
+    _fields_ = [("waves_per_group", C.c_int32), ("tile_w_log2", C.c_int32),
+                ("tiles_per_wave", C.c_int32), ("xcd_remap", C.c_int32)]
+
+
+class ClassifyT(C.Structure):
+    _fields_ = [("occ_threshold", C.c_float), ("free_threshold", C.c_float)]
+
+
+_vp = C.c_void_p
+_u32 = C.c_uint32
+
+
+def _sig(name, restype, *argtypes):
+    f = getattr(_lib, name)
+    f.restype = restype
+    f.argtypes = list(argtypes)
+    return f
+
+
+_sig("nbt_ig_abi_version", C.c_int)
+_sig("nbt_ig_status_string", C.c_char_p, C.c_int)
+_sig("nbt_ig_last_error", C.c_char_p)
+_sig("nbt_ig_ctx_create", C.c_int, C.c_int, C.POINTER(_vp))
+_sig("nbt_ig_ctx_destroy", None, _vp)
+_sig("nbt_ig_create_map", C.c_int, _vp, _vp, C.c_int, C.c_int, C.c_int, C.c_float,
+     C.POINTER(C.c_float), C.POINTER(ClassifyT), _vp, C.POINTER(_vp))
+_sig("nbt_ig_destroy_map", None, _vp)
+_sig("nbt_ig_map_info", C.c_int, _vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+     C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_size_t))
+_sig("nbt_ig_eval_viewpoints", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp, _vp)
+_sig("nbt_ig_trace_rays", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp)
+_sig("nbt_ig_trace_paths", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _u32, _u32, _vp, _vp, _vp)
+_sig("nbt_ig_ctx_set_launch", C.c_int, _vp, C.POINTER(LaunchT))
+_sig("nbt_ig_ctx_get_launch", C.c_int, _vp, C.POINTER(LaunchT))
+_sig("nbt_ig_camera_from_grid", C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+     C.POINTER(CameraT))
+
+
+def lib():
+    return _lib
+
+
+def abi_version() -> int:
+    return _lib.nbt_ig_abi_version()
+
+
+def status_string(s: int) -> str:
+    return _lib.nbt_ig_status_string(s).decode()
+
+
+def last_error() -> str:
+    return _lib.nbt_ig_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise NbtError(rc, f"{status_string(rc)}: {last_error()}")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    if stream is None:
+        torch = _torch()
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    return C.c_void_p(t.data_ptr())
+
+
+def camera(cam) -> CameraT:
+    """Accept a CameraT, an object with ``as_tuple()`` or (W, H, tan_h, tan_v, range)."""
+    if isinstance(cam, CameraT):
+        return cam
+    if hasattr(cam, "as_tuple"):
+        cam = cam.as_tuple()
+    w, h, th, tv, r = cam
+    return CameraT(int(w), int(h), float(th), float(tv), float(r))
+
+
+def camera_from_grid(fov_h, fov_v, d_cam, s_vox, s_g) -> CameraT:
+    out = CameraT()
+    _check(_lib.nbt_ig_camera_from_grid(fov_h, fov_v, d_cam, s_vox, s_g, C.byref(out)))
+    return out
+
+
+class Context:
+    """One device plus the reduction workspace (nbt_ig_ctx)."""
+
+    def __init__(self, device: int = 0):
+        h = _vp()
+        _check(_lib.nbt_ig_ctx_create(int(device), C.byref(h)))
+        self.handle = h
+        self.device = int(device)
+
+    def set_launch(self, waves_per_group=4, tile_w_log2=3, tiles_per_wave=1, xcd_remap=1):
+        _check(_lib.nbt_ig_ctx_set_launch(self.handle, C.byref(LaunchT(waves_per_group, tile_w_log2,
+                                                                        tiles_per_wave, xcd_remap))))
+
+    def get_launch(self):
+        l = LaunchT()
+        _check(_lib.nbt_ig_ctx_get_launch(self.handle, C.byref(l)))
+        return {"waves_per_group": l.waves_per_group, "tile_w_log2": l.tile_w_log2,
+                "tiles_per_wave": l.tiles_per_wave, "xcd_remap": l.xcd_remap}
+
+    def close(self):
+        if self.handle:
+            _lib.nbt_ig_ctx_destroy(self.handle)
+            self.handle = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Map:
+    """A device-resident encoded occupancy map (nbt_ig_map).
+
+    ``prob`` is float32 [nz, ny, nx]: a torch tensor (host or device) or a
+    NumPy array.  The library copies it.
+    """
+
+    def __init__(self, ctx: Context, prob, voxel: float, origin, thresholds=(0.5, 0.5), stream=None):
+        torch = _torch()
+        if not isinstance(prob, torch.Tensor):
+            prob = torch.from_numpy(prob)
+        if prob.dtype != torch.float32 or prob.dim() != 3:
+            raise ValueError("prob must be float32 [nz, ny, nx]")
+        prob = prob.contiguous()
+        nz, ny, nx = prob.shape
+        org = (C.c_float * 3)(*[float(v) for v in origin])
+        cls = ClassifyT(float(thresholds[0]), float(thresholds[1]))
+        h = _vp()
+        self.ctx = ctx
+        _check(_lib.nbt_ig_create_map(ctx.handle, C.c_void_p(prob.data_ptr()), nx, ny, nz, float(voxel),
+                                      org, C.byref(cls), _stream(stream), C.byref(h)))
+        self.handle = h
+        self.dims = (nx, ny, nz)
+        self.voxel = float(voxel)
+
+    def info(self):
+        nx, ny, nz = C.c_int(), C.c_int(), C.c_int()
+        vs = C.c_float()
+        org = (C.c_float * 3)()
+        nb = C.c_size_t()
+        _check(_lib.nbt_ig_map_info(self.handle, C.byref(nx), C.byref(ny), C.byref(nz), C.byref(vs),
+                                    org, C.byref(nb)))
+        return {"dims": (nx.value, ny.value, nz.value), "voxel": vs.value, "origin": tuple(org),
+                "device_bytes": nb.value}
+
+    def close(self):
+        if self.handle:
+            _lib.nbt_ig_destroy_map(self.handle)
+            self.handle = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def eval_viewpoints(m: Map, cam, poses, ig_out=None, steps_out=None, stream=None, want_steps=True):
+    """Per-perspective IG (float32 [N]) and voxel steps (int64 [N] holding uint64)."""
+    torch = _torch()
+    n = poses.shape[0]
+    dev = poses.device
+    if ig_out is None:
+        ig_out = torch.empty(n, dtype=torch.float32, device=dev)
+    if steps_out is None and want_steps:
+        steps_out = torch.empty(n, dtype=torch.int64, device=dev)
+    cm = camera(cam)
+    _check(_lib.nbt_ig_eval_viewpoints(m.handle, C.byref(cm), _dev_ptr(poses, torch.float32, "poses"), n,
+                                       _dev_ptr(ig_out, torch.float32, "ig_out"),
+                                       _dev_ptr(steps_out, torch.int64, "steps_out"), _stream(stream)))
+    return ig_out, steps_out
+
+
+def trace_rays(m: Map, cam, poses, out=None, stream=None):
+    """Per-ray records as a dict of tensors shaped [N, W*H]."""
+    torch = _torch()
+    cm = camera(cam)
+    n = poses.shape[0]
+    rays = cm.width * cm.height
+    if out is None:
+        out = torch.empty((n * rays, 8), dtype=torch.int32, device=poses.device)
+    _check(_lib.nbt_ig_trace_rays(m.handle, C.byref(cm), _dev_ptr(poses, torch.float32, "poses"), n,
+                                  _dev_ptr(out, torch.int32, "out"), _stream(stream)))
+    return {
+        "hash": out[:, 0:2].contiguous().view(torch.int64).view(n, rays),
+        "gain": out[:, 2:4].contiguous().view(torch.float64).view(n, rays),
+        "steps": out[:, 4].view(n, rays),
+        "stop_lin": out[:, 5].view(n, rays),
+        "reason": out[:, 6].view(n, rays),
+    }
+
+
+def trace_paths(m: Map, cam, poses, rays_sel, max_len, stream=None):
+    """Full voxel sequences for selected (pose, ray) pairs: (lin [count, max_len], len [count])."""
+    torch = _torch()
+    cm = camera(cam)
+    sel = rays_sel.to(device=poses.device, dtype=torch.int32).contiguous()
+    count = sel.shape[0]
+    lin = torch.full((count, max(int(max_len), 1)), -1, dtype=torch.int32, device=poses.device)
+    ln = torch.zeros(count, dtype=torch.int32, device=poses.device)
+    _check(_lib.nbt_ig_trace_paths(m.handle, C.byref(cm), _dev_ptr(poses, torch.float32, "poses"),
+                                   poses.shape[0], _dev_ptr(sel, None, "rays"), count, int(max_len),
+                                   _dev_ptr(lin, None, "lin"), _dev_ptr(ln, None, "len"), _stream(stream)))
+    return lin, ln

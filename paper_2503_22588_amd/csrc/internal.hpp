@@ -1,0 +1,81 @@
+// internal.hpp -- types shared by the library's translation units (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nbt_ig.h"
+
+namespace nbt {
+
+// Encoded voxel word: the Eq. 2 gain of the voxel as float32 bits, with the
+// sign bit set for Occupied voxels (their gain 1-P is still in the low 31
+// bits).  The one-voxel border around the map holds kSentinel, a negative
+// NaN pattern that no gain can take, so a single signed test per step
+// catches both "stop after this voxel" and "the walk left the map".
+constexpr uint32_t kSentinel = 0xFFFFFFFFu;
+constexpr uint32_t kOccBit = 0x80000000u;
+constexpr uint32_t kGainOne = 0x3F800000u;   // 1.0f: the gain of an Unknown voxel
+
+// Device view of an encoded map (passed to kernels by value).
+struct DevMap {
+    const uint32_t* enc;    // padded grid, x fastest: ((z+1)*py + (y+1))*px + (x+1)
+    uint32_t bytes;         // size of enc in bytes (< 2^32)
+    int nx, ny, nz;         // real dimensions
+    int px, py, pz;         // padded dimensions (n + 2)
+    float inv_s;            // 1/voxel_size (binary32)
+    float ox, oy, oz;       // origin
+};
+
+// Endpoint-grid parameters derived once per launch on the host.
+struct CamParams {
+    int W, H;
+    float dh, dv;           // range * tan(fov/2), binary32
+    float range;
+};
+
+// Per-perspective reduction slot used when several workgroups share one
+// perspective: fixed-point sums are order-independent, so the result is
+// bit-identical whatever order the workgroups finish in.  The last
+// workgroup of a perspective reads and clears its slot.
+struct VpAccum {
+    unsigned long long sum_fx;     // sum of ray gains * 2^24, rounded per workgroup
+    unsigned long long steps;
+    unsigned int count;            // workgroups done
+    unsigned int invalid;
+};
+constexpr double kFixScale = 16777216.0;     // 2^24
+
+// Launch shape of the viewpoint kernel.
+struct VpLaunch {
+    int waves;              // waves per workgroup (1, 2, 4, 8)
+    int tile_w_log2;        // pixel tile of one wave: (1<<tile_w_log2) x (64>>tile_w_log2)
+    int tiles_per_wave;     // tiles one wave walks per workgroup
+    int xcd_remap;          // spread consecutive perspectives over one XCD's L2
+};
+
+// ---- launchers (each defined next to its kernels) ----
+
+hipError_t launch_encode_map(const float* prob, uint32_t* enc, const DevMap& m, float occ_thr,
+                             float free_thr, unsigned int* bad_flag, hipStream_t s);
+
+hipError_t launch_eval_viewpoints(const DevMap& m, const CamParams& c, const float* poses,
+                                  uint32_t n, float* ig_out, unsigned long long* steps_out,
+                                  VpAccum* ws, const VpLaunch& L, hipStream_t s);
+
+hipError_t launch_trace_rays(const DevMap& m, const CamParams& c, const float* poses, uint32_t n,
+                             nbt_ig_ray_digest* out, hipStream_t s);
+
+hipError_t launch_trace_paths(const DevMap& m, const CamParams& c, const float* poses, uint32_t n,
+                              const uint32_t* rays, uint32_t count, uint32_t max_len,
+                              int32_t* lin_out, uint32_t* len_out, hipStream_t s);
+
+// Number of workgroups a perspective is split into for a launch shape.
+inline uint32_t vp_groups(const CamParams& c, const VpLaunch& L) {
+    const int tw = 1 << L.tile_w_log2, th = 64 >> L.tile_w_log2;
+    const uint32_t tiles = (uint32_t)((c.W + tw - 1) / tw) * (uint32_t)((c.H + th - 1) / th);
+    const uint32_t per = (uint32_t)(L.waves * L.tiles_per_wave);
+    return (tiles + per - 1) / per;
+}
+
+}  // namespace nbt

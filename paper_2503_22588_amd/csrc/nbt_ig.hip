@@ -1,0 +1,389 @@
+// nbt_ig.hip -- host side of the C ABI: validation, device memory, launches.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "internal.hpp"
+
+using namespace nbt;
+
+// ---------------------------------------------------------------- errors ----
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(e == hipErrorOutOfMemory ? NBT_IG_ENOMEM : NBT_IG_EDEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+// Makes the context's device current for the duration of a call and
+// restores the caller's device afterwards.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = (prev == dev) || (hipSetDevice(dev) == hipSuccess);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+bool finite_pos(float x) { return std::isfinite(x) && x > 0.0f; }
+
+}  // namespace
+
+// ---------------------------------------------------------------- objects ---
+
+struct nbt_ig_ctx {
+    int device = 0;
+    int cu_count = 0;
+    char arch[64] = {0};
+    std::mutex mu;
+    VpAccum* ws = nullptr;          // per-perspective reduction slots, kept zeroed
+    size_t ws_cap = 0;              // slots allocated
+    unsigned int* flag = nullptr;   // small scratch for map validation
+    VpLaunch vp_launch{4, 3, 1, 1}; // 4 waves, 8x8 tiles, 1 tile per wave, XCD remap
+};
+
+struct nbt_ig_map {
+    nbt_ig_ctx* ctx = nullptr;
+    DevMap dm{};
+    uint32_t* enc = nullptr;
+    size_t enc_bytes = 0;
+    float voxel = 0.0f;
+    float origin[3] = {0, 0, 0};
+    nbt_ig_classify cls{0.5f, 0.5f};
+};
+
+namespace {
+
+int ensure_workspace(nbt_ig_ctx* ctx, size_t slots) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->ws_cap >= slots) return NBT_IG_OK;
+    size_t cap = ctx->ws_cap ? ctx->ws_cap : 1024;
+    while (cap < slots) cap *= 2;
+    if (ctx->ws) {
+        hipError_t e = hipDeviceSynchronize();   // earlier launches may still use the old slots
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        (void)hipFree(ctx->ws);
+        ctx->ws = nullptr;
+        ctx->ws_cap = 0;
+    }
+    VpAccum* p = nullptr;
+    hipError_t e = hipMalloc(&p, cap * sizeof(VpAccum));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
+    e = hipMemset(p, 0, cap * sizeof(VpAccum));
+    if (e != hipSuccess) {
+        (void)hipFree(p);
+        return hip_fail(e, "hipMemset(workspace)");
+    }
+    ctx->ws = p;
+    ctx->ws_cap = cap;
+    return NBT_IG_OK;
+}
+
+int check_camera(const nbt_ig_camera* cam, CamParams* out) {
+    if (!cam) return fail(NBT_IG_EINVAL, "camera is NULL");
+    if (cam->width < 1 || cam->height < 1)
+        return fail(NBT_IG_EINVAL, "camera grid %ux%u: both sides must be >= 1", cam->width, cam->height);
+    if ((uint64_t)cam->width * cam->height > (1u << 22))
+        return fail(NBT_IG_EUNSUPPORTED, "camera grid %ux%u exceeds 2^22 rays per perspective",
+                    cam->width, cam->height);
+    if (!finite_pos(cam->tan_half_fov_h) || !finite_pos(cam->tan_half_fov_v) || !finite_pos(cam->range))
+        return fail(NBT_IG_EINVAL, "camera tangents and range must be finite and > 0");
+    out->W = (int)cam->width;
+    out->H = (int)cam->height;
+    out->range = cam->range;
+    out->dh = cam->range * cam->tan_half_fov_h;
+    out->dv = cam->range * cam->tan_half_fov_v;
+    return NBT_IG_OK;
+}
+
+int check_map(const nbt_ig_map* map) {
+    if (!map || !map->enc || !map->ctx) return fail(NBT_IG_EINVAL, "map is NULL or destroyed");
+    return NBT_IG_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- API -------
+
+extern "C" {
+
+int nbt_ig_abi_version(void) { return NBT_IG_ABI_VERSION; }
+
+const char* nbt_ig_last_error(void) { return g_last_error.c_str(); }
+
+const char* nbt_ig_status_string(int s) {
+    switch (s) {
+        case NBT_IG_OK: return "ok";
+        case NBT_IG_EINVAL: return "invalid argument";
+        case NBT_IG_ENOMEM: return "out of memory";
+        case NBT_IG_EDEVICE: return "device error";
+        case NBT_IG_EUNSUPPORTED: return "unsupported";
+        default: return "unknown status";
+    }
+}
+
+int nbt_ig_ctx_create(int device, nbt_ig_ctx** out) {
+    if (!out) return fail(NBT_IG_EINVAL, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= count)
+        return fail(NBT_IG_EINVAL, "device %d out of range (%d devices)", device, count);
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(NBT_IG_EUNSUPPORTED, "device %d is %s; this library is built for gfx950", device,
+                    prop.gcnArchName);
+    nbt_ig_ctx* ctx = new (std::nothrow) nbt_ig_ctx;
+    if (!ctx) return fail(NBT_IG_ENOMEM, "host allocation failed");
+    ctx->device = device;
+    ctx->cu_count = prop.multiProcessorCount;
+    std::snprintf(ctx->arch, sizeof ctx->arch, "%s", prop.gcnArchName);
+    DeviceGuard g(device);
+    e = hipMalloc(&ctx->flag, 256);
+    if (e != hipSuccess) {
+        delete ctx;
+        return hip_fail(e, "hipMalloc(flag)");
+    }
+    *out = ctx;
+    return NBT_IG_OK;
+}
+
+void nbt_ig_ctx_destroy(nbt_ig_ctx* ctx) {
+    if (!ctx) return;
+    DeviceGuard g(ctx->device);
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->flag) (void)hipFree(ctx->flag);
+    delete ctx;
+}
+
+int nbt_ig_create_map(nbt_ig_ctx* ctx, const float* prob, int nx, int ny, int nz, float voxel_size,
+                      const float origin[3], const nbt_ig_classify* cls, void* stream,
+                      nbt_ig_map** out) {
+    if (!out) return fail(NBT_IG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctx) return fail(NBT_IG_EINVAL, "ctx is NULL");
+    if (!prob || !origin) return fail(NBT_IG_EINVAL, "prob or origin is NULL");
+    if (nx < 1 || ny < 1 || nz < 1 || nx > 4096 || ny > 4096 || nz > 4096)
+        return fail(NBT_IG_EINVAL, "map dims %dx%dx%d outside [1, 4096]", nx, ny, nz);
+    const uint64_t padded = (uint64_t)(nx + 2) * (ny + 2) * (nz + 2);
+    if (padded >= (1ull << 30))
+        return fail(NBT_IG_EUNSUPPORTED, "map %dx%dx%d: padded size must stay below 2^30 voxels", nx, ny, nz);
+    if (!finite_pos(voxel_size)) return fail(NBT_IG_EINVAL, "voxel_size must be finite and > 0");
+    if (!std::isfinite(origin[0]) || !std::isfinite(origin[1]) || !std::isfinite(origin[2]))
+        return fail(NBT_IG_EINVAL, "origin must be finite");
+    nbt_ig_classify c = cls ? *cls : nbt_ig_classify{0.5f, 0.5f};
+    if (!(c.free_threshold >= 0.0f && c.free_threshold <= c.occ_threshold && c.occ_threshold <= 1.0f))
+        return fail(NBT_IG_EINVAL, "thresholds must satisfy 0 <= free <= occ <= 1");
+
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+
+    nbt_ig_map* map = new (std::nothrow) nbt_ig_map;
+    if (!map) return fail(NBT_IG_ENOMEM, "host allocation failed");
+    map->ctx = ctx;
+    map->voxel = voxel_size;
+    std::memcpy(map->origin, origin, sizeof map->origin);
+    map->cls = c;
+    map->enc_bytes = padded * 4;
+    hipError_t e = hipMalloc(&map->enc, map->enc_bytes);
+    if (e != hipSuccess) {
+        delete map;
+        return hip_fail(e, "hipMalloc(map)");
+    }
+    DevMap& dm = map->dm;
+    dm.enc = map->enc;
+    dm.bytes = (uint32_t)map->enc_bytes;
+    dm.nx = nx; dm.ny = ny; dm.nz = nz;
+    dm.px = nx + 2; dm.py = ny + 2; dm.pz = nz + 2;
+    dm.inv_s = 1.0f / voxel_size;
+    dm.ox = origin[0]; dm.oy = origin[1]; dm.oz = origin[2];
+
+    // Host or device source?  Host grids are staged through a device buffer.
+    const size_t src_bytes = (size_t)nx * ny * nz * sizeof(float);
+    const float* src = prob;
+    float* staged = nullptr;
+    hipPointerAttribute_t attr;
+    bool on_device = false;
+    if (hipPointerGetAttributes(&attr, prob) == hipSuccess)
+        on_device = attr.type == hipMemoryTypeDevice;
+    else
+        (void)hipGetLastError();
+    int rc = NBT_IG_OK;
+    unsigned int bad = 0;
+    if (!on_device) {
+        e = hipMalloc(&staged, src_bytes);
+        if (e != hipSuccess) { rc = hip_fail(e, "hipMalloc(staging)"); goto done; }
+        e = hipMemcpyAsync(staged, prob, src_bytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) { rc = hip_fail(e, "hipMemcpyAsync(prob)"); goto done; }
+        src = staged;
+    }
+    e = hipMemsetAsync(ctx->flag, 0, sizeof(unsigned int), s);
+    if (e != hipSuccess) { rc = hip_fail(e, "hipMemsetAsync(flag)"); goto done; }
+    e = launch_encode_map(src, map->enc, dm, c.occ_threshold, c.free_threshold, ctx->flag, s);
+    if (e != hipSuccess) { rc = hip_fail(e, "encode_map_kernel"); goto done; }
+    e = hipMemcpyAsync(&bad, ctx->flag, sizeof bad, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { rc = hip_fail(e, "map encode"); goto done; }
+    if (bad) rc = fail(NBT_IG_EINVAL, "occupancy probabilities must lie in [0, 1] (NaN found or out of range)");
+done:
+    if (staged) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(staged);
+    }
+    if (rc != NBT_IG_OK) {
+        (void)hipFree(map->enc);
+        delete map;
+        return rc;
+    }
+    *out = map;
+    return NBT_IG_OK;
+}
+
+void nbt_ig_destroy_map(nbt_ig_map* map) {
+    if (!map) return;
+    DeviceGuard g(map->ctx->device);
+    if (map->enc) (void)hipFree(map->enc);
+    map->enc = nullptr;
+    delete map;
+}
+
+int nbt_ig_map_info(const nbt_ig_map* map, int* nx, int* ny, int* nz, float* voxel_size,
+                    float origin[3], size_t* device_bytes) {
+    if (int rc = check_map(map)) return rc;
+    if (nx) *nx = map->dm.nx;
+    if (ny) *ny = map->dm.ny;
+    if (nz) *nz = map->dm.nz;
+    if (voxel_size) *voxel_size = map->voxel;
+    if (origin) std::memcpy(origin, map->origin, sizeof map->origin);
+    if (device_bytes) *device_bytes = map->enc_bytes;
+    return NBT_IG_OK;
+}
+
+int nbt_ig_eval_viewpoints(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                           uint32_t n, float* ig_out, uint64_t* steps_out, void* stream) {
+    if (int rc = check_map(map)) return rc;
+    CamParams c;
+    if (int rc = check_camera(cam, &c)) return rc;
+    if (n == 0) return NBT_IG_OK;
+    if (!poses || !ig_out) return fail(NBT_IG_EINVAL, "poses or ig_out is NULL");
+    nbt_ig_ctx* ctx = map->ctx;
+    const VpLaunch L = ctx->vp_launch;
+    const uint64_t groups = vp_groups(c, L);
+    if ((uint64_t)n * groups >= (1ull << 32))
+        return fail(NBT_IG_EUNSUPPORTED, "%u perspectives x %llu workgroups exceed the grid limit", n,
+                    (unsigned long long)groups);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", ctx->device);
+    if (groups > 1)
+        if (int rc = ensure_workspace(ctx, n)) return rc;
+    hipError_t e = launch_eval_viewpoints(map->dm, c, poses, n, ig_out,
+                                          reinterpret_cast<unsigned long long*>(steps_out), ctx->ws, L,
+                                          (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "ig_viewpoints_kernel");
+    return NBT_IG_OK;
+}
+
+int nbt_ig_trace_rays(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                      uint32_t n, nbt_ig_ray_digest* out, void* stream) {
+    if (int rc = check_map(map)) return rc;
+    CamParams c;
+    if (int rc = check_camera(cam, &c)) return rc;
+    if (n == 0) return NBT_IG_OK;
+    if (!poses || !out) return fail(NBT_IG_EINVAL, "poses or out is NULL");
+    if ((uint64_t)c.W * c.H * n / 256 + 1 >= (1ull << 31))
+        return fail(NBT_IG_EUNSUPPORTED, "too many rays for one trace launch");
+    DeviceGuard g(map->ctx->device);
+    if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", map->ctx->device);
+    hipError_t e = launch_trace_rays(map->dm, c, poses, n, out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "trace_rays_kernel");
+    return NBT_IG_OK;
+}
+
+int nbt_ig_trace_paths(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                       uint32_t n, const uint32_t* rays, uint32_t count, uint32_t max_len,
+                       int32_t* lin_out, uint32_t* len_out, void* stream) {
+    if (int rc = check_map(map)) return rc;
+    CamParams c;
+    if (int rc = check_camera(cam, &c)) return rc;
+    if (count == 0) return NBT_IG_OK;
+    if (!poses || !rays || !len_out || (max_len > 0 && !lin_out))
+        return fail(NBT_IG_EINVAL, "poses, rays, lin_out or len_out is NULL");
+    DeviceGuard g(map->ctx->device);
+    if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", map->ctx->device);
+    hipError_t e = launch_trace_paths(map->dm, c, poses, n, rays, count, max_len, lin_out, len_out,
+                                      (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "trace_paths_kernel");
+    return NBT_IG_OK;
+}
+
+int nbt_ig_ctx_set_launch(nbt_ig_ctx* ctx, const nbt_ig_launch* l) {
+    if (!ctx || !l) return fail(NBT_IG_EINVAL, "ctx or launch is NULL");
+    const int w = l->waves_per_group;
+    if (!(w == 1 || w == 2 || w == 4 || w == 8))
+        return fail(NBT_IG_EINVAL, "waves_per_group must be 1, 2, 4 or 8 (got %d)", w);
+    if (l->tile_w_log2 < 0 || l->tile_w_log2 > 6)
+        return fail(NBT_IG_EINVAL, "tile_w_log2 must be in 0..6 (got %d)", l->tile_w_log2);
+    if (l->tiles_per_wave < 1 || l->tiles_per_wave > 4096)
+        return fail(NBT_IG_EINVAL, "tiles_per_wave must be in 1..4096 (got %d)", l->tiles_per_wave);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->vp_launch = VpLaunch{w, l->tile_w_log2, l->tiles_per_wave, l->xcd_remap ? 1 : 0};
+    return NBT_IG_OK;
+}
+
+int nbt_ig_ctx_get_launch(const nbt_ig_ctx* ctx, nbt_ig_launch* l) {
+    if (!ctx || !l) return fail(NBT_IG_EINVAL, "ctx or launch is NULL");
+    l->waves_per_group = ctx->vp_launch.waves;
+    l->tile_w_log2 = ctx->vp_launch.tile_w_log2;
+    l->tiles_per_wave = ctx->vp_launch.tiles_per_wave;
+    l->xcd_remap = ctx->vp_launch.xcd_remap;
+    return NBT_IG_OK;
+}
+
+int nbt_ig_camera_from_grid(double fov_h, double fov_v, double d_cam, double s_vox, double s_g,
+                            nbt_ig_camera* out) {
+    if (!out) return fail(NBT_IG_EINVAL, "out is NULL");
+    if (!(fov_h > 0 && fov_h < M_PI && fov_v > 0 && fov_v < M_PI && d_cam > 0 && s_vox > 0 && s_g > 0) ||
+        !std::isfinite(d_cam) || !std::isfinite(s_vox) || !std::isfinite(s_g))
+        return fail(NBT_IG_EINVAL, "need 0 < fov < pi and finite d_cam, s_vox, s_g > 0");
+    const double th = std::tan(fov_h / 2.0), tv = std::tan(fov_v / 2.0);
+    const double spacing = s_g * s_vox;
+    // 1e-9 absorbs the rounding of tan() at exact multiples of the spacing
+    const double w = std::floor(2.0 * d_cam * th / spacing + 1e-9) + 1.0;
+    const double h = std::floor(2.0 * d_cam * tv / spacing + 1e-9) + 1.0;
+    if (w > 4194304.0 || h > 4194304.0 || w * h > 4194304.0)
+        return fail(NBT_IG_EUNSUPPORTED, "grid %.0fx%.0f exceeds 2^22 rays", w, h);
+    out->width = (uint32_t)w;
+    out->height = (uint32_t)h;
+    out->tan_half_fov_h = (float)th;
+    out->tan_half_fov_v = (float)tv;
+    out->range = (float)d_cam;
+    return NBT_IG_OK;
+}
+
+}  // extern "C"

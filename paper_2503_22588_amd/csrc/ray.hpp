@@ -1,0 +1,182 @@
+// ray.hpp -- per-lane ray generation and 3D-DDA state (device code).
+//
+// One lane owns one ray.  Set-up turns pixel (i, j) of a perspective into a
+// voxel-unit segment O -> O + D clipped to the map (Sec. III, endpoint
+// calculation), then into Amanatides-Woo traversal state.  Every operation
+// is a single binary32 operation in a fixed order (the library is built
+// with -ffp-contract=off, correctly rounded division and IEEE denormals), so
+// the visited voxel sequence is a deterministic function of the inputs.
+#pragma once
+
+#include "internal.hpp"
+
+namespace nbt {
+
+enum RayStatus : int { kRayOk = 0, kRayMiss = 1, kRayInvalid = 2 };
+
+struct RayState {
+    int ix, iy, iz;          // current voxel (real coordinates)
+    int sx, sy, sz;          // step direction per axis (-1, 0, +1)
+    float tx, ty, tz;        // parameter of the next face crossing per axis
+    float dtx, dty, dtz;     // parameter distance between crossings per axis
+    float t1;                // end of the clipped segment
+};
+
+__device__ __forceinline__ float sel_min(float a, float b) { return (b < a) ? b : a; }
+__device__ __forceinline__ float sel_max(float a, float b) { return (b > a) ? b : a; }
+
+// One axis of the slab clip.  Returns false when the ray runs parallel to
+// this axis' faces outside the map.
+__device__ __forceinline__ bool clip_axis(float O, float D, int n, float& t0, float& t1,
+                                          float& inv, bool& parallel) {
+    parallel = fabsf(D) < 0x1p-100f;
+    if (parallel) {
+        inv = 0.0f;
+        return (O >= 0.0f) && (O < (float)n);
+    }
+    inv = 1.0f / D;
+    const float tA = (0.0f - O) * inv;
+    const float tB = ((float)n - O) * inv;
+    t0 = sel_max(t0, sel_min(tA, tB));
+    t1 = sel_min(t1, sel_max(tA, tB));
+    return true;
+}
+
+__device__ __forceinline__ void init_axis(float O, float D, float t0, float inv, bool parallel,
+                                          int n, int& idx, int& step, float& tmax, float& tdelta) {
+    float f = floorf(O + t0 * D);
+    f = sel_max(f, 0.0f);
+    f = sel_min(f, (float)(n - 1));
+    idx = (int)f;
+    if (parallel) {
+        step = 0;
+        tmax = __builtin_inff();
+        tdelta = __builtin_inff();
+    } else {
+        step = D > 0.0f ? 1 : -1;
+        tdelta = fabsf(inv);
+        tmax = ((float)(idx + (step > 0 ? 1 : 0)) - O) * inv;
+    }
+}
+
+// pose: 12 floats (row-major R camera->world, then t).
+__device__ __forceinline__ int setup_ray(const DevMap& m, const CamParams& c, const float* pose,
+                                         int i, int j, RayState& r) {
+    float u = 0.0f, v = 0.0f;
+    if (c.W > 1) u = c.dh * ((float)(2 * i - (c.W - 1)) / (float)(c.W - 1));
+    if (c.H > 1) v = c.dv * ((float)(2 * j - (c.H - 1)) / (float)(c.H - 1));
+
+    const float org[3] = {m.ox, m.oy, m.oz};
+    float O[3], D[3];
+    bool finite = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float w = pose[3 * a + 0] * u;
+        w = w + pose[3 * a + 1] * v;
+        w = w + pose[3 * a + 2] * c.range;
+        const float t = pose[9 + a];
+        const float e = t + w;
+        O[a] = (t - org[a]) * m.inv_s;
+        const float E = (e - org[a]) * m.inv_s;
+        D[a] = E - O[a];
+        finite = finite && __builtin_isfinite(O[a]) && __builtin_isfinite(E) && __builtin_isfinite(D[a]);
+    }
+    if (!finite) return kRayInvalid;
+
+    float t0 = 0.0f, t1 = 1.0f;
+    float inv[3];
+    bool par[3];
+    const int n[3] = {m.nx, m.ny, m.nz};
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) inside = clip_axis(O[a], D[a], n[a], t0, t1, inv[a], par[a]) && inside;
+    if (!inside || t0 > t1) return kRayMiss;
+
+    init_axis(O[0], D[0], t0, inv[0], par[0], n[0], r.ix, r.sx, r.tx, r.dtx);
+    init_axis(O[1], D[1], t0, inv[1], par[1], n[1], r.iy, r.sy, r.ty, r.dty);
+    init_axis(O[2], D[2], t0, inv[2], par[2], n[2], r.iz, r.sz, r.tz, r.dtz);
+    r.t1 = t1;
+    return kRayOk;
+}
+
+// Buffer resource over the encoded grid: out-of-range offsets read 0 instead
+// of faulting, which keeps any indexing mistake inside the map's allocation.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t map_rsrc(const DevMap& m) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)m.enc, (short)0, (int)m.bytes, 0x00020000);
+}
+
+__device__ __forceinline__ uint32_t load_word(__amdgpu_buffer_rsrc_t rs, uint32_t byte_off) {
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)byte_off, 0, 0);
+}
+
+__device__ __forceinline__ uint32_t padded_offset(const DevMap& m, int x, int y, int z) {
+    return ((uint32_t)((z + 1) * m.py + (y + 1)) * (uint32_t)m.px + (uint32_t)(x + 1)) * 4u;
+}
+
+__device__ __forceinline__ unsigned long long fnv1a_u32(unsigned long long h, uint32_t v) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        h ^= (unsigned long long)((v >> (8 * b)) & 0xFFu);
+        h *= 0x100000001b3ULL;
+    }
+    return h;
+}
+
+constexpr unsigned long long kFnvBasis = 0xcbf29ce484222325ULL;
+
+// Reason a walk stopped (matches NBT_IG_RAY_*).
+enum WalkEnd : int { kEndHit = NBT_IG_RAY_HIT, kEndEnd = NBT_IG_RAY_END, kEndExit = NBT_IG_RAY_EXIT };
+
+// Walks one ray.  Per visited voxel the encoded word is gathered and its gain
+// added; the walk stops after an Occupied voxel, on the border sentinel (the
+// previous voxel was the last), or when the next face crossing lies beyond
+// the segment end.  The loop body is straight-line code with a single exit
+// test so that divergent lanes cost one mask update per step.  When TRACK is
+// set the voxel coordinates are kept and visit(x, y, z) runs for every
+// visited voxel.
+template <bool TRACK, class Visit>
+__device__ __forceinline__ int walk_ray(const DevMap& m, __amdgpu_buffer_rsrc_t rs, RayState& r,
+                                        double& acc, uint32_t& steps, Visit&& visit) {
+    const int dxo = r.sx * 4;
+    const int dyo = r.sy * m.px * 4;
+    const int dzo = r.sz * m.px * m.py * 4;
+    const float dtx = r.dtx, dty = r.dty, dtz = r.dtz;
+    uint32_t off = padded_offset(m, r.ix, r.iy, r.iz);
+    float tx = r.tx, ty = r.ty, tz = r.tz;
+    const float t1 = r.t1;
+    const uint32_t guard = (uint32_t)(m.nx + m.ny + m.nz + 3);
+    uint32_t n = 0;
+    uint32_t bits;
+    float tm;
+    for (;;) {
+        bits = load_word(rs, off);
+        const bool sentinel = bits == kSentinel;
+        const float g = sentinel ? 0.0f : __uint_as_float(bits & ~kOccBit);
+        acc += (double)g;
+        n += sentinel ? 0u : 1u;
+        if constexpr (TRACK) {
+            if (!sentinel) visit(r.ix, r.iy, r.iz);
+        }
+        tm = fminf(fminf(tx, ty), tz);
+        if ((int)bits < 0 || tm > t1 || n >= guard) break;
+        const bool bx = (tx == tm);
+        const bool by = !bx && (ty == tm);
+        const bool bz = !bx && !by;
+        off += bx ? dxo : (by ? dyo : dzo);
+        const float nt = tm + (bx ? dtx : (by ? dty : dtz));
+        tx = bx ? nt : tx;
+        ty = by ? nt : ty;
+        tz = bz ? nt : tz;
+        if constexpr (TRACK) {
+            r.ix += bx ? r.sx : 0;
+            r.iy += by ? r.sy : 0;
+            r.iz += bz ? r.sz : 0;
+        }
+    }
+    steps += n;
+    if ((int)bits < 0) return bits == kSentinel ? kEndExit : kEndHit;
+    if (tm > t1) return t1 == 1.0f ? kEndEnd : kEndExit;
+    return kEndExit;
+}
+
+}  // namespace nbt

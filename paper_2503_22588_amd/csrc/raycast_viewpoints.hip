@@ -1,0 +1,242 @@
+// raycast_viewpoints.hip -- per-perspective IG and the parity-mode ray records.
+//
+// Work decomposition: a perspective's N_E rays are cut into pixel tiles of
+// 64 rays, one tile per wavefront (one ray per lane).  Neighbouring pixels
+// have nearly parallel rays, so a wave's 64 gathers per step fall into a
+// few cache lines of the map.  A workgroup of WAVES waves covers
+// WAVES*tiles_per_wave tiles of one perspective; a perspective with more
+// tiles is split over several workgroups whose partial sums are combined in
+// fixed point (order independent), the last one writing g_P = sum / N_E
+// (Sec. III, IG calculation: the per-perspective mean of the ray gains).
+#include "ray.hpp"
+
+namespace nbt {
+
+// Consecutive workgroup ids are dealt round-robin to the 8 XCDs.  Remapping
+// gives each XCD a contiguous range of logical workgroups, i.e. of
+// perspectives, so perspectives that look at the same region share one L2.
+__device__ __forceinline__ uint32_t xcd_logical(uint32_t bid, uint32_t nb) {
+    constexpr uint32_t kXcd = 8;
+    const uint32_t xcd = bid % kXcd, slot = bid / kXcd;
+    const uint32_t full = nb / kXcd, rem = nb % kXcd;
+    return xcd * full + (xcd < rem ? xcd : rem) + slot;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ unsigned int wave_sum_u32(unsigned int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void ig_viewpoints_kernel(
+    DevMap m, CamParams c, const float* __restrict__ poses, uint32_t groups, uint32_t tiles_x,
+    uint32_t tiles, int tw_log2, int tpw, int remap, float* __restrict__ ig_out,
+    unsigned long long* __restrict__ steps_out, VpAccum* __restrict__ ws) {
+    const uint32_t bid = remap ? xcd_logical(blockIdx.x, gridDim.x) : blockIdx.x;
+    const uint32_t vp = bid / groups;
+    const uint32_t g = bid - vp * groups;
+
+    float pose[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) pose[k] = poses[12 * (size_t)vp + k];
+
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int tw = 1 << tw_log2;
+    const int th = 64 >> tw_log2;
+    const int lx = lane & (tw - 1);
+    const int ly = lane >> tw_log2;
+    const __amdgpu_buffer_rsrc_t rs = map_rsrc(m);
+
+    double acc = 0.0;
+    uint32_t steps = 0;
+    bool invalid = false;
+    for (int r = 0; r < tpw; ++r) {
+        const uint32_t tile = (g * WAVES + (uint32_t)wave) * (uint32_t)tpw + (uint32_t)r;
+        if (tile >= tiles) break;
+        const int i = (int)(tile % tiles_x) * tw + lx;
+        const int j = (int)(tile / tiles_x) * th + ly;
+        if (i < c.W && j < c.H) {
+            RayState ray;
+            const int st = setup_ray(m, c, pose, i, j, ray);
+            if (st == kRayOk)
+                walk_ray<false>(m, rs, ray, acc, steps, [](int, int, int) {});
+            else if (st == kRayInvalid)
+                invalid = true;
+        }
+    }
+
+    acc = wave_sum(acc);
+    steps = wave_sum_u32(steps);
+    const bool wave_invalid = __ballot(invalid) != 0ull;
+
+    __shared__ double s_acc[WAVES];
+    __shared__ unsigned long long s_steps[WAVES];
+    __shared__ int s_inv[WAVES];
+    if (lane == 0) {
+        s_acc[wave] = acc;
+        s_steps[wave] = steps;
+        s_inv[wave] = wave_invalid ? 1 : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+
+    double tot = 0.0;
+    unsigned long long st = 0;
+    int inv = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+        tot += s_acc[w];
+        st += s_steps[w];
+        inv |= s_inv[w];
+    }
+    const double rays = (double)c.W * (double)c.H;
+    if (groups == 1) {
+        ig_out[vp] = inv ? __builtin_nanf("") : (float)(tot / rays);
+        if (steps_out) steps_out[vp] = st;
+        return;
+    }
+    VpAccum* a = ws + vp;
+    atomicAdd(&a->sum_fx, __double2ull_rn(tot * kFixScale));
+    atomicAdd(&a->steps, st);
+    if (inv) atomicOr(&a->invalid, 1u);
+    __threadfence();
+    const unsigned int done = atomicAdd(&a->count, 1u);
+    if (done == groups - 1) {
+        __threadfence();
+        const unsigned long long s = atomicExch(&a->sum_fx, 0ull);
+        const unsigned long long stp = atomicExch(&a->steps, 0ull);
+        const unsigned int iv = atomicExch(&a->invalid, 0u);
+        atomicExch(&a->count, 0u);
+        ig_out[vp] = iv ? __builtin_nanf("") : (float)(((double)s / kFixScale) / rays);
+        if (steps_out) steps_out[vp] = stp;
+    }
+}
+
+// Parity mode: one thread per ray, full record per ray.
+__global__ __launch_bounds__(256) void trace_rays_kernel(DevMap m, CamParams c,
+                                                         const float* __restrict__ poses, uint32_t n,
+                                                         nbt_ig_ray_digest* __restrict__ out) {
+    const uint64_t rays = (uint64_t)c.W * (uint64_t)c.H;
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= rays * n) return;
+    const uint32_t vp = (uint32_t)(gid / rays);
+    const uint32_t k = (uint32_t)(gid - (uint64_t)vp * rays);
+    float pose[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) pose[q] = poses[12 * (size_t)vp + q];
+    const int i = (int)(k % (uint32_t)c.W), j = (int)(k / (uint32_t)c.W);
+
+    nbt_ig_ray_digest d;
+    d.hash = kFnvBasis;
+    d.gain = 0.0;
+    d.steps = 0;
+    d.stop_lin = -1;
+    d.reason = NBT_IG_RAY_MISS;
+    d.reserved = 0;
+    RayState ray;
+    const int st = setup_ray(m, c, pose, i, j, ray);
+    if (st == kRayInvalid) {
+        d.reason = NBT_IG_RAY_INVALID;
+        d.gain = __builtin_nan("");
+    } else if (st == kRayOk) {
+        unsigned long long h = kFnvBasis;
+        int32_t last = -1;
+        double acc = 0.0;
+        uint32_t steps = 0;
+        const int reason = walk_ray<true>(m, map_rsrc(m), ray, acc, steps,
+                                          [&](int x, int y, int z) {
+                                              last = (z * m.ny + y) * m.nx + x;
+                                              h = fnv1a_u32(h, (uint32_t)last);
+                                          });
+        d.hash = h;
+        d.gain = acc;
+        d.steps = steps;
+        d.stop_lin = last;
+        d.reason = (uint32_t)reason;
+    }
+    out[gid] = d;
+}
+
+__global__ __launch_bounds__(256) void trace_paths_kernel(DevMap m, CamParams c,
+                                                          const float* __restrict__ poses, uint32_t n,
+                                                          const uint32_t* __restrict__ sel,
+                                                          uint32_t count, uint32_t max_len,
+                                                          int32_t* __restrict__ lin_out,
+                                                          uint32_t* __restrict__ len_out) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= count) return;
+    const uint32_t vp = sel[2 * r], k = sel[2 * r + 1];
+    const uint32_t rays = (uint32_t)c.W * (uint32_t)c.H;
+    if (vp >= n || k >= rays) {
+        len_out[r] = 0;
+        return;
+    }
+    float pose[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) pose[q] = poses[12 * (size_t)vp + q];
+    RayState ray;
+    uint32_t steps = 0;
+    if (setup_ray(m, c, pose, (int)(k % (uint32_t)c.W), (int)(k / (uint32_t)c.W), ray) == kRayOk) {
+        double acc = 0.0;
+        int32_t* dst = lin_out + (size_t)r * max_len;
+        uint32_t w = 0;
+        walk_ray<true>(m, map_rsrc(m), ray, acc, steps, [&](int x, int y, int z) {
+            if (w < max_len) dst[w] = (z * m.ny + y) * m.nx + x;
+            ++w;
+        });
+    }
+    len_out[r] = steps;
+}
+
+hipError_t launch_eval_viewpoints(const DevMap& m, const CamParams& c, const float* poses,
+                                  uint32_t n, float* ig_out, unsigned long long* steps_out,
+                                  VpAccum* ws, const VpLaunch& L, hipStream_t s) {
+    const int tw = 1 << L.tile_w_log2, th = 64 >> L.tile_w_log2;
+    const uint32_t tiles_x = (uint32_t)((c.W + tw - 1) / tw);
+    const uint32_t tiles = tiles_x * (uint32_t)((c.H + th - 1) / th);
+    const uint32_t groups = vp_groups(c, L);
+    const dim3 grid((unsigned)((uint64_t)n * groups));
+    switch (L.waves) {
+#define NBT_VP_CASE(W)                                                                          \
+    case W:                                                                                     \
+        hipLaunchKernelGGL(ig_viewpoints_kernel<W>, grid, dim3(W * 64), 0, s, m, c, poses,      \
+                           groups, tiles_x, tiles, L.tile_w_log2, L.tiles_per_wave, L.xcd_remap, \
+                           ig_out, steps_out, ws);                                              \
+        break;
+        NBT_VP_CASE(1)
+        NBT_VP_CASE(2)
+        NBT_VP_CASE(4)
+        NBT_VP_CASE(8)
+#undef NBT_VP_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_rays(const DevMap& m, const CamParams& c, const float* poses, uint32_t n,
+                             nbt_ig_ray_digest* out, hipStream_t s) {
+    const uint64_t total = (uint64_t)c.W * c.H * n;
+    const uint64_t blocks = (total + 255) / 256;
+    hipLaunchKernelGGL(trace_rays_kernel, dim3((unsigned)blocks), dim3(256), 0, s, m, c, poses, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_paths(const DevMap& m, const CamParams& c, const float* poses, uint32_t n,
+                              const uint32_t* rays, uint32_t count, uint32_t max_len,
+                              int32_t* lin_out, uint32_t* len_out, hipStream_t s) {
+    const uint32_t blocks = (count + 255) / 256;
+    hipLaunchKernelGGL(trace_paths_kernel, dim3(blocks), dim3(256), 0, s, m, c, poses, n, rays,
+                       count, max_len, lin_out, len_out);
+    return hipGetLastError();
+}
+
+}  // namespace nbt
