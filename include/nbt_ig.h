@@ -127,6 +127,16 @@ int nbt_ig_create_map(nbt_ig_ctx* ctx, const float* prob, int nx, int ny, int nz
                       nbt_ig_map** out);
 void nbt_ig_destroy_map(nbt_ig_map* map);        /* NULL is a no-op */
 
+/* Re-encodes an existing map in place from new probabilities of the same
+ * dimensions (the map is rebuilt whenever a new point cloud has been fused,
+ * Sec. III).  `prob` is a DEVICE pointer; the call is asynchronous on
+ * `stream` and does not synchronise.  Values outside [0,1] or NaN are
+ * encoded as Unknown and recorded; nbt_ig_map_check() synchronises `stream`
+ * and returns NBT_IG_EINVAL if any update since the last check saw one.
+ * Evaluations already enqueued on other streams must finish first. */
+int nbt_ig_update_map(nbt_ig_map* map, const float* prob, void* stream);
+int nbt_ig_map_check(nbt_ig_map* map, void* stream);
+
 /* Dimensions of a map (HOST outputs, any may be NULL). */
 int nbt_ig_map_info(const nbt_ig_map* map, int* nx, int* ny, int* nz, float* voxel_size,
                     float origin[3], size_t* device_bytes);

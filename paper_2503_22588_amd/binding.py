@@ -66,6 +66,8 @@ _sig("nbt_ig_ctx_destroy", None, _vp)
 _sig("nbt_ig_create_map", C.c_int, _vp, _vp, C.c_int, C.c_int, C.c_int, C.c_float,
      C.POINTER(C.c_float), C.POINTER(ClassifyT), _vp, C.POINTER(_vp))
 _sig("nbt_ig_destroy_map", None, _vp)
+_sig("nbt_ig_update_map", C.c_int, _vp, _vp, _vp)
+_sig("nbt_ig_map_check", C.c_int, _vp, _vp)
 _sig("nbt_ig_map_info", C.c_int, _vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
      C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_size_t))
 _sig("nbt_ig_eval_viewpoints", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp, _vp)
@@ -195,6 +197,16 @@ class Map:
         self.handle = h
         self.dims = (nx, ny, nz)
         self.voxel = float(voxel)
+
+    def update(self, prob, stream=None):
+        """Re-encode in place from a device tensor of the same shape (asynchronous)."""
+        torch = _torch()
+        if tuple(prob.shape) != (self.dims[2], self.dims[1], self.dims[0]):
+            raise ValueError("prob shape differs from the map")
+        _check(_lib.nbt_ig_update_map(self.handle, _dev_ptr(prob, torch.float32, "prob"), _stream(stream)))
+
+    def check(self, stream=None):
+        _check(_lib.nbt_ig_map_check(self.handle, _stream(stream)))
 
     def info(self):
         nx, ny, nz = C.c_int(), C.c_int(), C.c_int()

@@ -60,12 +60,12 @@ struct nbt_ig_ctx {
     std::mutex mu;
     VpAccum* ws = nullptr;          // per-perspective reduction slots, kept zeroed
     size_t ws_cap = 0;              // slots allocated
-    unsigned int* flag = nullptr;   // small scratch for map validation
     VpLaunch vp_launch{4, 3, 1, 1}; // 4 waves, 8x8 tiles, 1 tile per wave, XCD remap
 };
 
 struct nbt_ig_map {
     nbt_ig_ctx* ctx = nullptr;
+    unsigned int* bad = nullptr;    // set by encodes that met an invalid probability
     DevMap dm{};
     uint32_t* enc = nullptr;
     size_t enc_bytes = 0;
@@ -163,12 +163,6 @@ int nbt_ig_ctx_create(int device, nbt_ig_ctx** out) {
     ctx->device = device;
     ctx->cu_count = prop.multiProcessorCount;
     std::snprintf(ctx->arch, sizeof ctx->arch, "%s", prop.gcnArchName);
-    DeviceGuard g(device);
-    e = hipMalloc(&ctx->flag, 256);
-    if (e != hipSuccess) {
-        delete ctx;
-        return hip_fail(e, "hipMalloc(flag)");
-    }
     *out = ctx;
     return NBT_IG_OK;
 }
@@ -177,7 +171,6 @@ void nbt_ig_ctx_destroy(nbt_ig_ctx* ctx) {
     if (!ctx) return;
     DeviceGuard g(ctx->device);
     if (ctx->ws) (void)hipFree(ctx->ws);
-    if (ctx->flag) (void)hipFree(ctx->flag);
     delete ctx;
 }
 
@@ -243,11 +236,13 @@ int nbt_ig_create_map(nbt_ig_ctx* ctx, const float* prob, int nx, int ny, int nz
         if (e != hipSuccess) { rc = hip_fail(e, "hipMemcpyAsync(prob)"); goto done; }
         src = staged;
     }
-    e = hipMemsetAsync(ctx->flag, 0, sizeof(unsigned int), s);
+    e = hipMalloc(&map->bad, sizeof(unsigned int));
+    if (e != hipSuccess) { rc = hip_fail(e, "hipMalloc(flag)"); goto done; }
+    e = hipMemsetAsync(map->bad, 0, sizeof(unsigned int), s);
     if (e != hipSuccess) { rc = hip_fail(e, "hipMemsetAsync(flag)"); goto done; }
-    e = launch_encode_map(src, map->enc, dm, c.occ_threshold, c.free_threshold, ctx->flag, s);
+    e = launch_encode_map(src, map->enc, dm, c.occ_threshold, c.free_threshold, map->bad, s);
     if (e != hipSuccess) { rc = hip_fail(e, "encode_map_kernel"); goto done; }
-    e = hipMemcpyAsync(&bad, ctx->flag, sizeof bad, hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(&bad, map->bad, sizeof bad, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) { rc = hip_fail(e, "map encode"); goto done; }
     if (bad) rc = fail(NBT_IG_EINVAL, "occupancy probabilities must lie in [0, 1] (NaN found or out of range)");
@@ -258,6 +253,7 @@ done:
     }
     if (rc != NBT_IG_OK) {
         (void)hipFree(map->enc);
+        if (map->bad) (void)hipFree(map->bad);
         delete map;
         return rc;
     }
@@ -269,8 +265,34 @@ void nbt_ig_destroy_map(nbt_ig_map* map) {
     if (!map) return;
     DeviceGuard g(map->ctx->device);
     if (map->enc) (void)hipFree(map->enc);
+    if (map->bad) (void)hipFree(map->bad);
     map->enc = nullptr;
     delete map;
+}
+
+int nbt_ig_update_map(nbt_ig_map* map, const float* prob, void* stream) {
+    if (int rc = check_map(map)) return rc;
+    if (!prob) return fail(NBT_IG_EINVAL, "prob is NULL");
+    DeviceGuard g(map->ctx->device);
+    if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", map->ctx->device);
+    hipError_t e = launch_encode_map(prob, map->enc, map->dm, map->cls.occ_threshold,
+                                     map->cls.free_threshold, map->bad, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "encode_map_kernel");
+    return NBT_IG_OK;
+}
+
+int nbt_ig_map_check(nbt_ig_map* map, void* stream) {
+    if (int rc = check_map(map)) return rc;
+    DeviceGuard g(map->ctx->device);
+    if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", map->ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    unsigned int bad = 0;
+    hipError_t e = hipMemcpyAsync(&bad, map->bad, sizeof bad, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemsetAsync(map->bad, 0, sizeof bad, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "map check");
+    if (bad) return fail(NBT_IG_EINVAL, "an update met probabilities outside [0, 1] or NaN");
+    return NBT_IG_OK;
 }
 
 int nbt_ig_map_info(const nbt_ig_map* map, int* nx, int* ny, int* nz, float* voxel_size,

@@ -6,7 +6,8 @@ axis = viewing direction) followed by the camera centre ``t`` in world
 coordinates.  Perspectives look from their start point toward the point of
 interest (Sec. III, perspective selection); the roll about the viewing axis
 is fixed by keeping the camera x axis horizontal (world +Z is "up"), falling
-back to world +Y when the view is within 0.8 degrees of vertical.
+back to world +Y when the view is within 0.8 degrees of vertical.  A camera
+placed exactly at its target looks straight down.
 """
 
 from __future__ import annotations
@@ -24,8 +25,10 @@ def look_at(positions, poi):
     q = np.broadcast_to(np.asarray(poi, dtype=np.float64), p.shape)
     z = q - p
     nrm = np.linalg.norm(z, axis=1, keepdims=True)
-    nrm[nrm == 0] = 1.0
+    degenerate = nrm[:, 0] == 0
+    nrm[degenerate] = 1.0
     z = z / nrm
+    z[degenerate] = (0.0, 0.0, -1.0)          # no view vector: look straight down
     up = np.zeros_like(z)
     near_vertical = np.abs(z[:, 2]) > 0.9999
     up[~near_vertical, 2] = 1.0
