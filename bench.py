@@ -69,7 +69,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--launch", default=None, help="waves,tile_w_log2,tiles_per_wave,xcd_remap")
+    ap.add_argument("--launch", default=None,
+                    help="waves,tile_w_log2,tiles_per_wave,xcd_remap,pipeline_depth")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -81,6 +84,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "dispatches": 5}), flush=True)
+        return
 
     import paper_2503_22588_amd as nbt
     from workloads import make_config

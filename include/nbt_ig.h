@@ -173,7 +173,8 @@ int nbt_ig_trace_paths(const nbt_ig_map* map, const nbt_ig_camera* cam, const fl
  * {1,2,4,8} wavefronts per workgroup; each wave walks pixel tiles of
  * (1<<tile_w_log2) x (64>>tile_w_log2) rays (tile_w_log2 in 0..6);
  * tiles_per_wave >= 1 tiles per wave per workgroup; xcd_remap != 0 gives
- * each of the 8 XCDs a contiguous range of perspectives.  Any shape gives
+ * each of the 8 XCDs a contiguous range of perspectives; pipeline_depth in
+ * {1,2,4,8} map gathers in flight per ray (0 = default).  Any shape gives
  * the same step counts; IG agrees to the last-place rounding of its sum.
  */
 typedef struct {
@@ -181,6 +182,7 @@ typedef struct {
     int32_t tile_w_log2;
     int32_t tiles_per_wave;
     int32_t xcd_remap;
+    int32_t pipeline_depth;
 } nbt_ig_launch;
 
 int nbt_ig_ctx_set_launch(nbt_ig_ctx* ctx, const nbt_ig_launch* launch);

@@ -40,7 +40,7 @@ class CameraT(C.Structure):
 
 class LaunchT(C.Structure):
     _fields_ = [("waves_per_group", C.c_int32), ("tile_w_log2", C.c_int32),
-                ("tiles_per_wave", C.c_int32), ("xcd_remap", C.c_int32)]
+                ("tiles_per_wave", C.c_int32), ("xcd_remap", C.c_int32), ("pipeline_depth", C.c_int32)]
 
 
 class ClassifyT(C.Structure):
@@ -151,15 +151,17 @@ class Context:
         self.handle = h
         self.device = int(device)
 
-    def set_launch(self, waves_per_group=4, tile_w_log2=3, tiles_per_wave=1, xcd_remap=1):
+    def set_launch(self, waves_per_group=4, tile_w_log2=3, tiles_per_wave=16, xcd_remap=0, pipeline_depth=0):
         _check(_lib.nbt_ig_ctx_set_launch(self.handle, C.byref(LaunchT(waves_per_group, tile_w_log2,
-                                                                        tiles_per_wave, xcd_remap))))
+                                                                        tiles_per_wave, xcd_remap,
+                                                                        pipeline_depth))))
 
     def get_launch(self):
         l = LaunchT()
         _check(_lib.nbt_ig_ctx_get_launch(self.handle, C.byref(l)))
         return {"waves_per_group": l.waves_per_group, "tile_w_log2": l.tile_w_log2,
-                "tiles_per_wave": l.tiles_per_wave, "xcd_remap": l.xcd_remap}
+                "tiles_per_wave": l.tiles_per_wave, "xcd_remap": l.xcd_remap,
+                "pipeline_depth": l.pipeline_depth}
 
     def close(self):
         if self.handle:

@@ -52,6 +52,7 @@ struct VpLaunch {
     int tile_w_log2;        // pixel tile of one wave: (1<<tile_w_log2) x (64>>tile_w_log2)
     int tiles_per_wave;     // tiles one wave walks per workgroup
     int xcd_remap;          // spread consecutive perspectives over one XCD's L2
+    int depth;              // gathers in flight per lane (1, 2, 4, 8)
 };
 
 // ---- launchers (each defined next to its kernels) ----

@@ -60,7 +60,7 @@ struct nbt_ig_ctx {
     std::mutex mu;
     VpAccum* ws = nullptr;          // per-perspective reduction slots, kept zeroed
     size_t ws_cap = 0;              // slots allocated
-    VpLaunch vp_launch{4, 3, 1, 1}; // 4 waves, 8x8 tiles, 1 tile per wave, XCD remap
+    VpLaunch vp_launch{4, 3, 16, 0, 4}; // 4 waves, 8x8 tiles, 16 tiles/wave, no remap, 4 gathers in flight
 };
 
 struct nbt_ig_map {
@@ -373,8 +373,11 @@ int nbt_ig_ctx_set_launch(nbt_ig_ctx* ctx, const nbt_ig_launch* l) {
         return fail(NBT_IG_EINVAL, "tile_w_log2 must be in 0..6 (got %d)", l->tile_w_log2);
     if (l->tiles_per_wave < 1 || l->tiles_per_wave > 4096)
         return fail(NBT_IG_EINVAL, "tiles_per_wave must be in 1..4096 (got %d)", l->tiles_per_wave);
+    const int d = l->pipeline_depth == 0 ? 4 : l->pipeline_depth;
+    if (!(d == 1 || d == 2 || d == 4 || d == 8))
+        return fail(NBT_IG_EINVAL, "pipeline_depth must be 0 (default), 1, 2, 4 or 8 (got %d)", d);
     std::lock_guard<std::mutex> lk(ctx->mu);
-    ctx->vp_launch = VpLaunch{w, l->tile_w_log2, l->tiles_per_wave, l->xcd_remap ? 1 : 0};
+    ctx->vp_launch = VpLaunch{w, l->tile_w_log2, l->tiles_per_wave, l->xcd_remap ? 1 : 0, d};
     return NBT_IG_OK;
 }
 
@@ -384,6 +387,7 @@ int nbt_ig_ctx_get_launch(const nbt_ig_ctx* ctx, nbt_ig_launch* l) {
     l->tile_w_log2 = ctx->vp_launch.tile_w_log2;
     l->tiles_per_wave = ctx->vp_launch.tiles_per_wave;
     l->xcd_remap = ctx->vp_launch.xcd_remap;
+    l->pipeline_depth = ctx->vp_launch.depth;
     return NBT_IG_OK;
 }
 

@@ -179,4 +179,79 @@ __device__ __forceinline__ int walk_ray(const DevMap& m, __amdgpu_buffer_rsrc_t 
     return kEndExit;
 }
 
+// Words at or above this value are the border sentinel; every Occupied word
+// lies in 0x80000000..0xBF800000.
+constexpr uint32_t kMarkerMin = 0xBF800001u;
+
+// One generator step of the pipelined walk: move to the next voxel unless
+// the next face crossing lies beyond the segment end.  Past the end the
+// generator points at offset 0, the sentinel word in the corner of the
+// border, so every later gather reads "stop" without the loaded value ever
+// being inspected here (which would force a wait for it).  Loop invariants
+// are passed by value so that the axis choice stays a register select.
+__device__ __forceinline__ void dda_advance(float& tx, float& ty, float& tz, uint32_t& off,
+                                            bool& alive, float t1, int dxo, int dyo, int dzo,
+                                            float dtx, float dty, float dtz) {
+    const float x = tx, y = ty, z = tz;
+    const float tm = fminf(fminf(x, y), z);
+    const bool go = alive && !(tm > t1);
+    const bool ex = x == tm, ey = y == tm;
+    const bool bx = go && ex;
+    const bool by = go && !ex && ey;
+    const bool bz = go && !ex && !ey;
+    off = go ? off + (bx ? dxo : (by ? dyo : dzo)) : 0u;
+    const float nt = tm + (bx ? dtx : (by ? dty : dtz));
+    tx = bx ? nt : x;
+    ty = by ? nt : y;
+    tz = bz ? nt : z;
+    alive = go;
+}
+
+// Software-pipelined walk for the throughput kernels.  The voxel sequence of
+// a ray depends only on its geometry, never on the map contents, so a
+// generator runs P-1 voxels ahead of the consumer and keeps P gathers in
+// flight per lane; the consumer adds gains in visiting order and stops at
+// the first Occupied word or at a sentinel (the border, or the corner word
+// the generator reads once the segment has ended).  Visits, gains and their
+// order are exactly those of walk_ray; only the reason is not reported.
+// Gathers past a stop are never consumed (and out-of-range ones read 0).
+template <int P>
+__device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buffer_rsrc_t rs,
+                                                   const RayState& r, double& acc, uint32_t& steps) {
+    const int dxo = r.sx * 4;
+    const int dyo = r.sy * m.px * 4;
+    const int dzo = r.sz * m.px * m.py * 4;
+    const float dtx = r.dtx, dty = r.dty, dtz = r.dtz;
+    const float t1 = r.t1;
+    uint32_t off = padded_offset(m, r.ix, r.iy, r.iz);
+    float tx = r.tx, ty = r.ty, tz = r.tz;
+    const uint32_t guard = (uint32_t)(m.nx + m.ny + m.nz + 3);
+    bool alive = true;     // the generator has not yet passed the segment end
+
+    uint32_t w[P];
+    w[0] = load_word(rs, off);
+#pragma unroll
+    for (int u = 1; u < P; ++u) {
+        dda_advance(tx, ty, tz, off, alive, t1, dxo, dyo, dzo, dtx, dty, dtz);
+        w[u] = load_word(rs, off);
+    }
+    uint32_t n = 0;
+    bool run = true;
+    while (run) {
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            if (run) {
+                const uint32_t x = w[u];
+                const bool marker = x >= kMarkerMin;
+                acc += (double)__uint_as_float(marker ? 0u : (x & ~kOccBit));
+                n += marker ? 0u : 1u;
+                run = !((int)x < 0 || n >= guard);
+                dda_advance(tx, ty, tz, off, alive, t1, dxo, dyo, dzo, dtx, dty, dtz);
+                w[u] = load_word(rs, off);
+            }
+        }
+    }
+    steps += n;
+}
+
 }  // namespace nbt

@@ -8,6 +8,8 @@
 // tiles is split over several workgroups whose partial sums are combined in
 // fixed point (order independent), the last one writing g_P = sum / N_E
 // (Sec. III, IG calculation: the per-perspective mean of the ray gains).
+#include <tuple>
+
 #include "ray.hpp"
 
 namespace nbt {
@@ -34,7 +36,7 @@ __device__ __forceinline__ unsigned int wave_sum_u32(unsigned int v) {
     return v;
 }
 
-template <int WAVES>
+template <int WAVES, int DEPTH>
 __global__ __launch_bounds__(WAVES * 64) void ig_viewpoints_kernel(
     DevMap m, CamParams c, const float* __restrict__ poses, uint32_t groups, uint32_t tiles_x,
     uint32_t tiles, int tw_log2, int tpw, int remap, float* __restrict__ ig_out,
@@ -66,8 +68,12 @@ __global__ __launch_bounds__(WAVES * 64) void ig_viewpoints_kernel(
         if (i < c.W && j < c.H) {
             RayState ray;
             const int st = setup_ray(m, c, pose, i, j, ray);
-            if (st == kRayOk)
-                walk_ray<false>(m, rs, ray, acc, steps, [](int, int, int) {});
+            if (st == kRayOk) {
+                if constexpr (DEPTH == 1)
+                    walk_ray<false>(m, rs, ray, acc, steps, [](int, int, int) {});
+                else
+                    walk_ray_pipelined<DEPTH>(m, rs, ray, acc, steps);
+            }
             else if (st == kRayInvalid)
                 invalid = true;
         }
@@ -204,21 +210,31 @@ hipError_t launch_eval_viewpoints(const DevMap& m, const CamParams& c, const flo
     const uint32_t tiles = tiles_x * (uint32_t)((c.H + th - 1) / th);
     const uint32_t groups = vp_groups(c, L);
     const dim3 grid((unsigned)((uint64_t)n * groups));
-    switch (L.waves) {
-#define NBT_VP_CASE(W)                                                                          \
-    case W:                                                                                     \
-        hipLaunchKernelGGL(ig_viewpoints_kernel<W>, grid, dim3(W * 64), 0, s, m, c, poses,      \
-                           groups, tiles_x, tiles, L.tile_w_log2, L.tiles_per_wave, L.xcd_remap, \
-                           ig_out, steps_out, ws);                                              \
+    const auto args = std::make_tuple(m, c, poses, groups, tiles_x, tiles, L.tile_w_log2,
+                                      L.tiles_per_wave, L.xcd_remap, ig_out, steps_out, ws);
+    auto go = [&](auto kernel, int waves) {
+        std::apply([&](auto... a) { hipLaunchKernelGGL(kernel, grid, dim3(waves * 64), 0, s, a...); },
+                   args);
+    };
+#define NBT_VP_DEPTHS(W)                                          \
+    case W:                                                       \
+        switch (L.depth) {                                        \
+            case 1: go(ig_viewpoints_kernel<W, 1>, W); break;     \
+            case 2: go(ig_viewpoints_kernel<W, 2>, W); break;     \
+            case 4: go(ig_viewpoints_kernel<W, 4>, W); break;     \
+            case 8: go(ig_viewpoints_kernel<W, 8>, W); break;     \
+            default: return hipErrorInvalidValue;                 \
+        }                                                         \
         break;
-        NBT_VP_CASE(1)
-        NBT_VP_CASE(2)
-        NBT_VP_CASE(4)
-        NBT_VP_CASE(8)
-#undef NBT_VP_CASE
+    switch (L.waves) {
+        NBT_VP_DEPTHS(1)
+        NBT_VP_DEPTHS(2)
+        NBT_VP_DEPTHS(4)
+        NBT_VP_DEPTHS(8)
         default:
             return hipErrorInvalidValue;
     }
+#undef NBT_VP_DEPTHS
     return hipGetLastError();
 }
 

@@ -101,17 +101,17 @@ def test_cfg1_ig_and_steps(nbt, ctx):
     assert nan_ok and rel <= IG_RTOL, rel
 
 
-@pytest.mark.parametrize("shape", [(1, 3, 1, 0), (2, 3, 2, 1), (4, 4, 1, 1), (8, 2, 3, 0), (4, 6, 1, 1),
-                                   (4, 0, 2, 1), (8, 3, 8, 1)])
+@pytest.mark.parametrize("shape", [(1, 3, 1, 0, 1), (2, 3, 2, 1, 2), (4, 4, 1, 1, 4), (8, 2, 3, 0, 8),
+                                   (4, 6, 1, 1, 1), (4, 0, 2, 1, 4), (8, 3, 8, 1, 2), (1, 3, 5, 1, 8)])
 def test_launch_shapes_agree(nbt, ctx, shape):
     import torch
-    waves, twl, tpw, remap = shape
+    waves, twl, tpw, remap, depth = shape
     sc = scene_spheres(n=(48, 40, 36), voxel=0.06, n_spheres=18, seed=301, origin=(-1.0, 0.5, 0.25))
     cam = Camera(37, 23, 64, 48, 1.7)           # ragged: not a multiple of any tile side
     poses = poses_sphere(sc.poi, 0.7, 21, seed=302)
     _note(f"launch shape {shape}")
     m = _map(nbt, ctx, sc)
-    ctx.set_launch(waves, twl, tpw, remap)
+    ctx.set_launch(waves, twl, tpw, remap, depth)
     try:
         ig, st = nbt.eval_viewpoints(m, cam, _dev(poses))
         torch.cuda.synchronize()
