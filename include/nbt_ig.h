@@ -151,6 +151,29 @@ int nbt_ig_map_info(const nbt_ig_map* map, int* nx, int* ny, int* nz, float* vox
 int nbt_ig_eval_viewpoints(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
                            uint32_t n, float* ig_out, uint64_t* steps_out, void* stream);
 
+/* ---- per-trajectory IG ----------------------------------------------------------
+ * A trajectory is poses_per_traj consecutive poses: poses is float32
+ * [n_traj][poses_per_traj][12].  U_t = the set of voxels visited by any ray
+ * of any pose of trajectory t (the walk of Sec. III, each voxel counted
+ * once however often it is seen along the path).  Outputs (DEVICE):
+ *   ig_union[t]    sum over U_t of the Eq. 2 gains (binary64, rounded once to
+ *                  float32); NaN if any ray of the trajectory is INVALID;
+ *   counts[4t+0..3] |U_t|, occupied, free and unknown voxels of U_t (exact);
+ *   visits[t]      total voxel visits of all its rays (exact; may be NULL).
+ * Each trajectory's visited set is a bitset over the voxel box holding its
+ * frusta, kept in LDS when it fits the context's LDS budget and in global
+ * memory otherwise (allocated on demand).  The call synchronises `stream`
+ * once (to size the launch).  n_traj == 0 is a no-op.
+ */
+int nbt_ig_eval_trajectories(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                             uint32_t n_traj, uint32_t poses_per_traj, float* ig_union,
+                             uint32_t* counts, uint64_t* visits, void* stream);
+
+/* LDS per workgroup that trajectory bitsets may use (0 = the device maximum);
+ * larger boxes use global memory.  Context properties (HOST outputs, may be NULL). */
+int nbt_ig_ctx_set_lds_budget(nbt_ig_ctx* ctx, size_t bytes);
+int nbt_ig_ctx_info(const nbt_ig_ctx* ctx, int* cu_count, size_t* lds_per_group, size_t* lds_budget);
+
 /* ---- parity mode ---------------------------------------------------------------
  * One nbt_ig_ray_digest per ray: out[p*N_E + k] for pose p, ray k.
  */
@@ -172,8 +195,10 @@ int nbt_ig_trace_paths(const nbt_ig_map* map, const nbt_ig_camera* cam, const fl
  * How nbt_ig_eval_viewpoints maps rays to the GPU: waves_per_group in
  * {1,2,4,8} wavefronts per workgroup; each wave walks pixel tiles of
  * (1<<tile_w_log2) x (64>>tile_w_log2) rays (tile_w_log2 in 0..6);
- * tiles_per_wave >= 1 tiles per wave per workgroup; xcd_remap != 0 gives
- * each of the 8 XCDs a contiguous range of perspectives; pipeline_depth in
+ * tiles_per_wave >= 1 tiles per wave per workgroup; xcd_remap = C > 0
+ * deals runs of C consecutive workgroups (the workgroups of neighbouring
+ * perspectives) to one XCD and its L2, 0 keeps the hardware's round-robin
+ * order (C <= 65536); pipeline_depth in
  * {1,2,4,8} map gathers in flight per ray (0 = default).  Any shape gives
  * the same step counts; IG agrees to the last-place rounding of its sum.
  */

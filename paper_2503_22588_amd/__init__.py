@@ -8,12 +8,12 @@ package fails when the library has not been built.
 from . import binding
 from .binding import (
     NbtError, Context, Map, CameraT, camera, camera_from_grid,
-    eval_viewpoints, trace_rays, trace_paths,
+    eval_viewpoints, eval_trajectories, trace_rays, trace_paths,
     RAY_MISS, RAY_HIT, RAY_END, RAY_EXIT, RAY_INVALID,
 )
 
 __all__ = [
     "binding", "NbtError", "Context", "Map", "CameraT", "camera", "camera_from_grid",
-    "eval_viewpoints", "trace_rays", "trace_paths",
+    "eval_viewpoints", "eval_trajectories", "trace_rays", "trace_paths",
     "RAY_MISS", "RAY_HIT", "RAY_END", "RAY_EXIT", "RAY_INVALID",
 ]

@@ -71,6 +71,9 @@ _sig("nbt_ig_map_check", C.c_int, _vp, _vp)
 _sig("nbt_ig_map_info", C.c_int, _vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
      C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_size_t))
 _sig("nbt_ig_eval_viewpoints", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp, _vp)
+_sig("nbt_ig_eval_trajectories", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _u32, _vp, _vp, _vp, _vp)
+_sig("nbt_ig_ctx_set_lds_budget", C.c_int, _vp, C.c_size_t)
+_sig("nbt_ig_ctx_info", C.c_int, _vp, C.POINTER(C.c_int), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t))
 _sig("nbt_ig_trace_rays", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp)
 _sig("nbt_ig_trace_paths", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _u32, _u32, _vp, _vp, _vp)
 _sig("nbt_ig_ctx_set_launch", C.c_int, _vp, C.POINTER(LaunchT))
@@ -163,6 +166,14 @@ class Context:
                 "tiles_per_wave": l.tiles_per_wave, "xcd_remap": l.xcd_remap,
                 "pipeline_depth": l.pipeline_depth}
 
+    def set_lds_budget(self, nbytes=0):
+        _check(_lib.nbt_ig_ctx_set_lds_budget(self.handle, int(nbytes)))
+
+    def info(self):
+        cu, lds, budget = C.c_int(), C.c_size_t(), C.c_size_t()
+        _check(_lib.nbt_ig_ctx_info(self.handle, C.byref(cu), C.byref(lds), C.byref(budget)))
+        return {"cu_count": cu.value, "lds_per_group": lds.value, "lds_budget": budget.value}
+
     def close(self):
         if self.handle:
             _lib.nbt_ig_ctx_destroy(self.handle)
@@ -246,6 +257,21 @@ def eval_viewpoints(m: Map, cam, poses, ig_out=None, steps_out=None, stream=None
                                        _dev_ptr(ig_out, torch.float32, "ig_out"),
                                        _dev_ptr(steps_out, torch.int64, "steps_out"), _stream(stream)))
     return ig_out, steps_out
+
+
+def eval_trajectories(m: Map, cam, poses, stream=None):
+    """Union IG per trajectory: poses float32 [T, L, 12] -> (ig [T], counts [T,4] int32, visits [T] int64)."""
+    torch = _torch()
+    T, L = int(poses.shape[0]), int(poses.shape[1])
+    dev = poses.device
+    ig = torch.empty(T, dtype=torch.float32, device=dev)
+    counts = torch.empty((T, 4), dtype=torch.int32, device=dev)
+    visits = torch.empty(T, dtype=torch.int64, device=dev)
+    cm = camera(cam)
+    _check(_lib.nbt_ig_eval_trajectories(m.handle, C.byref(cm), _dev_ptr(poses, torch.float32, "poses"), T, L,
+                                         _dev_ptr(ig, torch.float32, "ig"), _dev_ptr(counts, None, "counts"),
+                                         _dev_ptr(visits, None, "visits"), _stream(stream)))
+    return ig, counts, visits
 
 
 def trace_rays(m: Map, cam, poses, out=None, stream=None):

@@ -51,8 +51,23 @@ struct VpLaunch {
     int waves;              // waves per workgroup (1, 2, 4, 8)
     int tile_w_log2;        // pixel tile of one wave: (1<<tile_w_log2) x (64>>tile_w_log2)
     int tiles_per_wave;     // tiles one wave walks per workgroup
-    int xcd_remap;          // spread consecutive perspectives over one XCD's L2
+    int xcd_remap;          // 0, or runs of this many consecutive workgroups per XCD
     int depth;              // gathers in flight per lane (1, 2, 4, 8)
+};
+
+// Voxel box of one trajectory's frusta and where its visited-voxel bitset lives.
+struct TrajBox {
+    int lx, ly, lz;          // min corner (voxels)
+    int ax, ay, az;          // extent (voxels)
+    uint32_t nbits;          // ax*ay*az, 0 for an empty trajectory
+    uint32_t global;         // 1: bitset in global memory at word offset goff
+    unsigned long long goff;
+};
+
+struct TrajMeta {
+    unsigned int max_bits;           // largest box routed to LDS
+    unsigned int n_global;           // trajectories routed to global memory
+    unsigned long long global_words; // 32-bit words of their bitsets (64-word aligned)
 };
 
 // ---- launchers (each defined next to its kernels) ----
@@ -70,6 +85,18 @@ hipError_t launch_trace_rays(const DevMap& m, const CamParams& c, const float* p
 hipError_t launch_trace_paths(const DevMap& m, const CamParams& c, const float* poses, uint32_t n,
                               const uint32_t* rays, uint32_t count, uint32_t max_len,
                               int32_t* lin_out, uint32_t* len_out, hipStream_t s);
+
+hipError_t launch_traj_boxes(const DevMap& m, const CamParams& c, const float* poses, uint32_t T,
+                             uint32_t L, uint32_t budget_bits, TrajBox* boxes, TrajMeta* meta,
+                             uint32_t* over_list, hipStream_t s);
+
+// Static LDS of the union kernel (its reductions); the bitset gets the rest.
+size_t traj_static_lds_bytes();
+
+hipError_t launch_traj_union(bool global, const DevMap& m, const CamParams& c, const float* poses,
+                             uint32_t L, uint32_t grid, size_t lds_bytes, const TrajBox* boxes,
+                             const uint32_t* over_list, uint32_t* gbits, float* ig_union,
+                             uint32_t* counts, unsigned long long* visits, hipStream_t s);
 
 // Number of workgroups a perspective is split into for a launch shape.
 inline uint32_t vp_groups(const CamParams& c, const VpLaunch& L) {

@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -61,6 +62,16 @@ struct nbt_ig_ctx {
     VpAccum* ws = nullptr;          // per-perspective reduction slots, kept zeroed
     size_t ws_cap = 0;              // slots allocated
     VpLaunch vp_launch{4, 3, 16, 0, 4}; // 4 waves, 8x8 tiles, 16 tiles/wave, no remap, 4 gathers in flight
+    size_t lds_max = 0;             // device limit of LDS per workgroup (bytes)
+    size_t lds_budget = 0;          // LDS a trajectory bitset may use (bytes)
+    // trajectory workspace
+    TrajBox* boxes = nullptr;
+    uint32_t* over_list = nullptr;
+    size_t traj_cap = 0;
+    TrajMeta* meta = nullptr;       // device
+    TrajMeta* meta_host = nullptr;  // pinned
+    uint32_t* gbits = nullptr;
+    size_t gbits_words = 0;
 };
 
 struct nbt_ig_map {
@@ -98,6 +109,51 @@ int ensure_workspace(nbt_ig_ctx* ctx, size_t slots) {
     }
     ctx->ws = p;
     ctx->ws_cap = cap;
+    return NBT_IG_OK;
+}
+
+int ensure_traj_workspace(nbt_ig_ctx* ctx, size_t T) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipError_t e;
+    if (!ctx->meta) {
+        if ((e = hipMalloc(&ctx->meta, sizeof(TrajMeta))) != hipSuccess) return hip_fail(e, "hipMalloc(meta)");
+        if ((e = hipHostMalloc(&ctx->meta_host, sizeof(TrajMeta))) != hipSuccess)
+            return hip_fail(e, "hipHostMalloc(meta)");
+    }
+    if (ctx->traj_cap >= T) return NBT_IG_OK;
+    size_t cap = ctx->traj_cap ? ctx->traj_cap : 1024;
+    while (cap < T) cap *= 2;
+    if (ctx->boxes) {
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        (void)hipFree(ctx->boxes);
+        (void)hipFree(ctx->over_list);
+        ctx->boxes = nullptr;
+        ctx->over_list = nullptr;
+        ctx->traj_cap = 0;
+    }
+    if ((e = hipMalloc(&ctx->boxes, cap * sizeof(TrajBox))) != hipSuccess) return hip_fail(e, "hipMalloc(boxes)");
+    if ((e = hipMalloc(&ctx->over_list, cap * sizeof(uint32_t))) != hipSuccess) {
+        (void)hipFree(ctx->boxes);
+        ctx->boxes = nullptr;
+        return hip_fail(e, "hipMalloc(over_list)");
+    }
+    ctx->traj_cap = cap;
+    return NBT_IG_OK;
+}
+
+int ensure_global_bits(nbt_ig_ctx* ctx, size_t words) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->gbits_words >= words) return NBT_IG_OK;
+    hipError_t e;
+    if (ctx->gbits) {
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        (void)hipFree(ctx->gbits);
+        ctx->gbits = nullptr;
+        ctx->gbits_words = 0;
+    }
+    if ((e = hipMalloc(&ctx->gbits, words * sizeof(uint32_t))) != hipSuccess)
+        return hip_fail(e, "hipMalloc(trajectory bitsets)");
+    ctx->gbits_words = words;
     return NBT_IG_OK;
 }
 
@@ -162,6 +218,14 @@ int nbt_ig_ctx_create(int device, nbt_ig_ctx** out) {
     if (!ctx) return fail(NBT_IG_ENOMEM, "host allocation failed");
     ctx->device = device;
     ctx->cu_count = prop.multiProcessorCount;
+    {
+        DeviceGuard g(device);
+        size_t lds = prop.sharedMemPerBlock;
+        if (lds > 160 * 1024) lds = 160 * 1024;
+        const size_t fixed = traj_static_lds_bytes();
+        ctx->lds_max = lds > fixed + 256 ? (lds - fixed - 256) / 256 * 256 : 0;
+        ctx->lds_budget = ctx->lds_max;
+    }
     std::snprintf(ctx->arch, sizeof ctx->arch, "%s", prop.gcnArchName);
     *out = ctx;
     return NBT_IG_OK;
@@ -171,6 +235,11 @@ void nbt_ig_ctx_destroy(nbt_ig_ctx* ctx) {
     if (!ctx) return;
     DeviceGuard g(ctx->device);
     if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->boxes) (void)hipFree(ctx->boxes);
+    if (ctx->over_list) (void)hipFree(ctx->over_list);
+    if (ctx->meta) (void)hipFree(ctx->meta);
+    if (ctx->meta_host) (void)hipHostFree(ctx->meta_host);
+    if (ctx->gbits) (void)hipFree(ctx->gbits);
     delete ctx;
 }
 
@@ -331,6 +400,66 @@ int nbt_ig_eval_viewpoints(const nbt_ig_map* map, const nbt_ig_camera* cam, cons
     return NBT_IG_OK;
 }
 
+int nbt_ig_eval_trajectories(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                             uint32_t n_traj, uint32_t poses_per_traj, float* ig_union,
+                             uint32_t* counts, uint64_t* visits, void* stream) {
+    if (int rc = check_map(map)) return rc;
+    CamParams c;
+    if (int rc = check_camera(cam, &c)) return rc;
+    if (n_traj == 0) return NBT_IG_OK;
+    if (!ig_union || !counts || (poses_per_traj > 0 && !poses))
+        return fail(NBT_IG_EINVAL, "poses, ig_union or counts is NULL");
+    const uint64_t tiles = (uint64_t)((c.W + 7) / 8) * ((c.H + 7) / 8) * poses_per_traj;
+    if (tiles >= (1ull << 31)) return fail(NBT_IG_EUNSUPPORTED, "too many rays per trajectory");
+    nbt_ig_ctx* ctx = map->ctx;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", ctx->device);
+    if (int rc = ensure_traj_workspace(ctx, n_traj)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t budget_bits = (uint32_t)std::min<size_t>(ctx->lds_budget * 8, 0xFFFFFFFFull);
+    hipError_t e = hipMemsetAsync(ctx->meta, 0, sizeof(TrajMeta), s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(meta)");
+    e = launch_traj_boxes(map->dm, c, poses, n_traj, poses_per_traj, budget_bits, ctx->boxes, ctx->meta,
+                          ctx->over_list, s);
+    if (e != hipSuccess) return hip_fail(e, "traj_box_kernel");
+    e = hipMemcpyAsync(ctx->meta_host, ctx->meta, sizeof(TrajMeta), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "trajectory boxes");
+    const TrajMeta meta = *ctx->meta_host;
+    unsigned long long* vis = reinterpret_cast<unsigned long long*>(visits);
+    if (meta.n_global < n_traj) {
+        const size_t lds = ((size_t)meta.max_bits + 31) / 32 * 4;
+        e = launch_traj_union(false, map->dm, c, poses, poses_per_traj, n_traj, lds ? lds : 4, ctx->boxes,
+                              ctx->over_list, nullptr, ig_union, counts, vis, s);
+        if (e != hipSuccess)
+            return fail(e == hipErrorOutOfMemory ? NBT_IG_ENOMEM : NBT_IG_EDEVICE,
+                        "traj_union_kernel(lds, %zu bytes of %zu): %s", lds, ctx->lds_max,
+                        hipGetErrorString(e));
+    }
+    if (meta.n_global > 0) {
+        if (int rc = ensure_global_bits(ctx, meta.global_words)) return rc;
+        e = launch_traj_union(true, map->dm, c, poses, poses_per_traj, meta.n_global, 0, ctx->boxes,
+                              ctx->over_list, ctx->gbits, ig_union, counts, vis, s);
+        if (e != hipSuccess) return hip_fail(e, "traj_union_kernel(global)");
+    }
+    return NBT_IG_OK;
+}
+
+int nbt_ig_ctx_set_lds_budget(nbt_ig_ctx* ctx, size_t bytes) {
+    if (!ctx) return fail(NBT_IG_EINVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->lds_budget = (bytes == 0 || bytes > ctx->lds_max) ? ctx->lds_max : bytes;
+    return NBT_IG_OK;
+}
+
+int nbt_ig_ctx_info(const nbt_ig_ctx* ctx, int* cu_count, size_t* lds_per_group, size_t* lds_budget) {
+    if (!ctx) return fail(NBT_IG_EINVAL, "ctx is NULL");
+    if (cu_count) *cu_count = ctx->cu_count;
+    if (lds_per_group) *lds_per_group = ctx->lds_max;
+    if (lds_budget) *lds_budget = ctx->lds_budget;
+    return NBT_IG_OK;
+}
+
 int nbt_ig_trace_rays(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
                       uint32_t n, nbt_ig_ray_digest* out, void* stream) {
     if (int rc = check_map(map)) return rc;
@@ -373,11 +502,13 @@ int nbt_ig_ctx_set_launch(nbt_ig_ctx* ctx, const nbt_ig_launch* l) {
         return fail(NBT_IG_EINVAL, "tile_w_log2 must be in 0..6 (got %d)", l->tile_w_log2);
     if (l->tiles_per_wave < 1 || l->tiles_per_wave > 4096)
         return fail(NBT_IG_EINVAL, "tiles_per_wave must be in 1..4096 (got %d)", l->tiles_per_wave);
+    if (l->xcd_remap < 0 || l->xcd_remap > 65536)
+        return fail(NBT_IG_EINVAL, "xcd_remap must be in 0..65536 (got %d)", l->xcd_remap);
     const int d = l->pipeline_depth == 0 ? 4 : l->pipeline_depth;
     if (!(d == 1 || d == 2 || d == 4 || d == 8))
         return fail(NBT_IG_EINVAL, "pipeline_depth must be 0 (default), 1, 2, 4 or 8 (got %d)", d);
     std::lock_guard<std::mutex> lk(ctx->mu);
-    ctx->vp_launch = VpLaunch{w, l->tile_w_log2, l->tiles_per_wave, l->xcd_remap ? 1 : 0, d};
+    ctx->vp_launch = VpLaunch{w, l->tile_w_log2, l->tiles_per_wave, l->xcd_remap, d};
     return NBT_IG_OK;
 }
 

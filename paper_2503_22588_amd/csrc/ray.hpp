@@ -254,4 +254,79 @@ __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buf
     steps += n;
 }
 
+// dda_advance plus a second index (a bitset position) that moves with the
+// map offset: by dbx/dby/dbz per step on x/y/z, and stays put once the
+// segment has ended.
+__device__ __forceinline__ void dda_advance_idx(float& tx, float& ty, float& tz, uint32_t& off,
+                                                int& idx, bool& alive, float t1, int dxo, int dyo,
+                                                int dzo, int dbx, int dby, int dbz, float dtx,
+                                                float dty, float dtz) {
+    const float x = tx, y = ty, z = tz;
+    const float tm = fminf(fminf(x, y), z);
+    const bool go = alive && !(tm > t1);
+    const bool ex = x == tm, ey = y == tm;
+    const bool bx = go && ex;
+    const bool by = go && !ex && ey;
+    const bool bz = go && !ex && !ey;
+    off = go ? off + (bx ? dxo : (by ? dyo : dzo)) : 0u;
+    idx = go ? idx + (bx ? dbx : (by ? dby : dbz)) : idx;
+    const float nt = tm + (bx ? dtx : (by ? dty : dtz));
+    tx = bx ? nt : x;
+    ty = by ? nt : y;
+    tz = bz ? nt : z;
+    alive = go;
+}
+
+// Pipelined walk that also reports every visited voxel as a bit index into a
+// bitset over the box [lo, lo + (ax, ay, *)): ((z-lz)*ay + (y-ly))*ax + (x-lx).
+// mark(bit) runs for each visited voxel in visiting order; indices at or
+// beyond nbits (a voxel outside the box, impossible when the box contains
+// the ray's frustum) are skipped.  Returns the number of voxels visited.
+template <int P, class Mark>
+__device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buffer_rsrc_t rs,
+                                                  const RayState& r, int lx, int ly, int lz, int ax,
+                                                  int ay, uint32_t nbits, Mark&& mark) {
+    const int dxo = r.sx * 4;
+    const int dyo = r.sy * m.px * 4;
+    const int dzo = r.sz * m.px * m.py * 4;
+    const int dbx = r.sx, dby = r.sy * ax, dbz = r.sz * ax * ay;
+    const float dtx = r.dtx, dty = r.dty, dtz = r.dtz;
+    const float t1 = r.t1;
+    uint32_t off = padded_offset(m, r.ix, r.iy, r.iz);
+    int bidx = ((r.iz - lz) * ay + (r.iy - ly)) * ax + (r.ix - lx);
+    float tx = r.tx, ty = r.ty, tz = r.tz;
+    const uint32_t guard = (uint32_t)(m.nx + m.ny + m.nz + 3);
+    bool alive = true;
+
+    uint32_t w[P];
+    int bi[P];
+    w[0] = load_word(rs, off);
+    bi[0] = bidx;
+#pragma unroll
+    for (int u = 1; u < P; ++u) {
+        dda_advance_idx(tx, ty, tz, off, bidx, alive, t1, dxo, dyo, dzo, dbx, dby, dbz, dtx, dty, dtz);
+        w[u] = load_word(rs, off);
+        bi[u] = bidx;
+    }
+    uint32_t n = 0;
+    bool run = true;
+    while (run) {
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            if (run) {
+                const uint32_t x = w[u];
+                const bool marker = x >= kMarkerMin;
+                if (!marker && (uint32_t)bi[u] < nbits) mark((uint32_t)bi[u]);
+                n += marker ? 0u : 1u;
+                run = !((int)x < 0 || n >= guard);
+                dda_advance_idx(tx, ty, tz, off, bidx, alive, t1, dxo, dyo, dzo, dbx, dby, dbz, dtx,
+                                dty, dtz);
+                w[u] = load_word(rs, off);
+                bi[u] = bidx;
+            }
+        }
+    }
+    return n;
+}
+
 }  // namespace nbt

@@ -1,0 +1,229 @@
+// raycast_trajectories.hip -- union information gain of camera trajectories.
+//
+// A trajectory of L poses sees the union U of the voxels visited by all rays
+// of all its poses; each voxel counts once however many rays or poses meet it
+// (a voxel seen again along the path brings no new information).  One
+// workgroup owns one trajectory and keeps U as a bitset over the voxel box
+// that contains every frustum of the trajectory:
+//   1. a pre-pass computes the box per trajectory (apex + 4 far-plane corners
+//      per pose, one voxel of margin, clipped to the map) and routes boxes
+//      that fit the LDS budget to the LDS kernel, the rest to global memory;
+//   2. the union kernel walks all L x N_E rays (one ray per lane, 8x8 tiles
+//      per wave, pipelined gathers) and sets one bit per visited voxel with
+//      an atomic OR (idempotent, so the set does not depend on thread order);
+//   3. the epilogue scans the bitset in a fixed order: |U|, per-state counts
+//      (exact integers) and the summed Eq. 2 gains of U (binary64).
+#include <tuple>
+
+#include "internal.hpp"
+#include "ray.hpp"
+#include "reduce.hpp"
+
+namespace nbt {
+
+constexpr int kTrajWaves = 16;
+
+__global__ __launch_bounds__(256) void traj_box_kernel(DevMap m, CamParams c,
+                                                       const float* __restrict__ poses, uint32_t T,
+                                                       uint32_t L, uint32_t budget_bits,
+                                                       TrajBox* __restrict__ boxes,
+                                                       TrajMeta* __restrict__ meta,
+                                                       uint32_t* __restrict__ over_list) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    const float org[3] = {m.ox, m.oy, m.oz};
+    const int n[3] = {m.nx, m.ny, m.nz};
+    const float u_lo = c.W > 1 ? -c.dh : 0.0f, u_hi = c.W > 1 ? c.dh : 0.0f;
+    const float v_lo = c.H > 1 ? -c.dv : 0.0f, v_hi = c.H > 1 ? c.dv : 0.0f;
+    float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+    float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+    bool unbounded = false;
+    for (uint32_t l = 0; l < L; ++l) {
+        const float* p = poses + 12 * ((size_t)t * L + l);
+        for (int q = 0; q < 5; ++q) {
+            const float u = q == 0 ? 0.0f : ((q & 1) ? u_lo : u_hi);
+            const float v = q == 0 ? 0.0f : ((q & 2) ? v_lo : v_hi);
+            const float d = q == 0 ? 0.0f : c.range;
+            for (int a = 0; a < 3; ++a) {
+                float w = p[3 * a + 0] * u;
+                w = w + p[3 * a + 1] * v;
+                w = w + p[3 * a + 2] * d;
+                const float e = (q == 0) ? p[9 + a] : p[9 + a] + w;
+                const float vx = (e - org[a]) * m.inv_s;
+                if (!__builtin_isfinite(vx)) unbounded = true;
+                lo[a] = vx < lo[a] ? vx : lo[a];
+                hi[a] = vx > hi[a] ? vx : hi[a];
+            }
+        }
+    }
+    int ilo[3], ihi[3];
+    for (int a = 0; a < 3; ++a) {
+        if (unbounded) {
+            ilo[a] = 0;
+            ihi[a] = n[a] - 1;
+        } else {
+            const float fl = floorf(lo[a]) - 1.0f, fh = floorf(hi[a]) + 1.0f;
+            const float cl = fl < 0.0f ? 0.0f : (fl > (float)(n[a] - 1) ? (float)(n[a] - 1) : fl);
+            const float ch = fh < 0.0f ? 0.0f : (fh > (float)(n[a] - 1) ? (float)(n[a] - 1) : fh);
+            ilo[a] = (int)cl;
+            ihi[a] = (int)ch;
+        }
+    }
+    TrajBox b;
+    b.lx = ilo[0]; b.ly = ilo[1]; b.lz = ilo[2];
+    b.ax = ihi[0] - ilo[0] + 1; b.ay = ihi[1] - ilo[1] + 1; b.az = ihi[2] - ilo[2] + 1;
+    b.nbits = (L == 0) ? 0u : (uint32_t)b.ax * (uint32_t)b.ay * (uint32_t)b.az;
+    b.global = 0;
+    b.goff = 0;
+    if (b.nbits <= budget_bits) {
+        atomicMax(&meta->max_bits, b.nbits);
+    } else {
+        b.global = 1;
+        const unsigned long long words = ((unsigned long long)b.nbits + 31) / 32;
+        b.goff = atomicAdd(&meta->global_words, (words + 63) / 64 * 64);
+        over_list[atomicAdd(&meta->n_global, 1u)] = t;
+    }
+    boxes[t] = b;
+}
+
+template <bool GLOBAL>
+__global__ __launch_bounds__(kTrajWaves * 64) void traj_union_kernel(
+    DevMap m, CamParams c, const float* __restrict__ poses, uint32_t L,
+    const TrajBox* __restrict__ boxes, const uint32_t* __restrict__ over_list,
+    uint32_t* __restrict__ gbits, float* __restrict__ ig_union, uint32_t* __restrict__ counts,
+    unsigned long long* __restrict__ visits) {
+    extern __shared__ uint32_t lds_bits[];
+    const uint32_t t = GLOBAL ? over_list[blockIdx.x] : blockIdx.x;
+    const TrajBox b = boxes[t];
+    if (!GLOBAL && b.global) return;
+    uint32_t* bits = GLOBAL ? gbits + b.goff : lds_bits;
+    const uint32_t nwords = (b.nbits + 31) / 32;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t w = tid; w < nwords; w += blockDim.x) bits[w] = 0u;
+    __syncthreads();
+
+    const int wave = tid >> 6, lane = tid & 63;
+    const int lx = lane & 7, ly = lane >> 3;
+    const uint32_t tiles_x = (uint32_t)(c.W + 7) / 8;
+    const uint32_t tiles_pose = tiles_x * (uint32_t)((c.H + 7) / 8);
+    const uint32_t total = tiles_pose * L;
+    const __amdgpu_buffer_rsrc_t rs = map_rsrc(m);
+    uint32_t steps = 0;
+    bool invalid = false;
+    for (uint32_t tile = (uint32_t)wave; tile < total; tile += kTrajWaves) {
+        const uint32_t l = tile / tiles_pose;
+        const uint32_t tt = tile - l * tiles_pose;
+        const float* pp = poses + 12 * ((size_t)t * L + l);
+        float pose[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) pose[k] = pp[k];
+        const int i = (int)(tt % tiles_x) * 8 + lx;
+        const int j = (int)(tt / tiles_x) * 8 + ly;
+        if (i < c.W && j < c.H) {
+            RayState ray;
+            const int st = setup_ray(m, c, pose, i, j, ray);
+            if (st == kRayOk) {
+                steps += walk_ray_mark<4>(m, rs, ray, b.lx, b.ly, b.lz, b.ax, b.ay, b.nbits,
+                                          [&](uint32_t bit) { atomicOr(&bits[bit >> 5], 1u << (bit & 31)); });
+            } else if (st == kRayInvalid) {
+                invalid = true;
+            }
+        }
+    }
+    __syncthreads();
+
+    // Epilogue: classify the voxels of U from their encoded words.
+    uint32_t c_occ = 0, c_free = 0, c_unk = 0;
+    double gain = 0.0;
+    const int axy = b.ax * b.ay;
+    for (uint32_t w = tid; w < nwords; w += blockDim.x) {
+        uint32_t word = GLOBAL ? __hip_atomic_load(&bits[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                               : bits[w];
+        while (word) {
+            const int bit = __ffs(word) - 1;
+            word &= word - 1u;
+            const int idx = (int)(w * 32u) + bit;
+            const int z = idx / axy;
+            const int rem = idx - z * axy;
+            const int y = rem / b.ax;
+            const int x = rem - y * b.ax;
+            const uint32_t e = load_word(rs, padded_offset(m, b.lx + x, b.ly + y, b.lz + z));
+            gain += (double)__uint_as_float(e & ~kOccBit);
+            if (e & kOccBit) ++c_occ;
+            else if (e == kGainOne) ++c_unk;
+            else ++c_free;
+        }
+    }
+    gain = wave_sum(gain);
+    c_occ = wave_sum_u32(c_occ);
+    c_free = wave_sum_u32(c_free);
+    c_unk = wave_sum_u32(c_unk);
+    const unsigned long long st = wave_sum_u64((unsigned long long)steps);
+    const bool wave_invalid = __ballot(invalid) != 0ull;
+    __shared__ double s_gain[kTrajWaves];
+    __shared__ unsigned long long s_steps[kTrajWaves];
+    __shared__ uint32_t s_cnt[kTrajWaves][3];
+    __shared__ int s_inv[kTrajWaves];
+    if (lane == 0) {
+        s_gain[wave] = gain;
+        s_steps[wave] = st;
+        s_cnt[wave][0] = c_occ;
+        s_cnt[wave][1] = c_free;
+        s_cnt[wave][2] = c_unk;
+        s_inv[wave] = wave_invalid ? 1 : 0;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    double g = 0.0;
+    unsigned long long vs = 0;
+    uint32_t co = 0, cf = 0, cu = 0;
+    int inv = 0;
+#pragma unroll
+    for (int w = 0; w < kTrajWaves; ++w) {
+        g += s_gain[w];
+        vs += s_steps[w];
+        co += s_cnt[w][0];
+        cf += s_cnt[w][1];
+        cu += s_cnt[w][2];
+        inv |= s_inv[w];
+    }
+    ig_union[t] = inv ? __builtin_nanf("") : (float)g;
+    counts[4 * (size_t)t + 0] = co + cf + cu;
+    counts[4 * (size_t)t + 1] = co;
+    counts[4 * (size_t)t + 2] = cf;
+    counts[4 * (size_t)t + 3] = cu;
+    if (visits) visits[t] = vs;
+}
+
+size_t traj_static_lds_bytes() {
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, (const void*)traj_union_kernel<false>) != hipSuccess) return 4096;
+    return a.sharedSizeBytes;
+}
+
+hipError_t launch_traj_boxes(const DevMap& m, const CamParams& c, const float* poses, uint32_t T,
+                             uint32_t L, uint32_t budget_bits, TrajBox* boxes, TrajMeta* meta,
+                             uint32_t* over_list, hipStream_t s) {
+    hipLaunchKernelGGL(traj_box_kernel, dim3((T + 255) / 256), dim3(256), 0, s, m, c, poses, T, L,
+                       budget_bits, boxes, meta, over_list);
+    return hipGetLastError();
+}
+
+hipError_t launch_traj_union(bool global, const DevMap& m, const CamParams& c, const float* poses,
+                             uint32_t L, uint32_t grid, size_t lds_bytes, const TrajBox* boxes,
+                             const uint32_t* over_list, uint32_t* gbits, float* ig_union,
+                             uint32_t* counts, unsigned long long* visits, hipStream_t s) {
+    if (global) {
+        hipLaunchKernelGGL(traj_union_kernel<true>, dim3(grid), dim3(kTrajWaves * 64), 0, s, m, c,
+                           poses, L, boxes, over_list, gbits, ig_union, counts, visits);
+    } else {
+        hipError_t e = hipFuncSetAttribute((const void*)traj_union_kernel<false>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(traj_union_kernel<false>, dim3(grid), dim3(kTrajWaves * 64), lds_bytes, s,
+                           m, c, poses, L, boxes, over_list, gbits, ig_union, counts, visits);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace nbt

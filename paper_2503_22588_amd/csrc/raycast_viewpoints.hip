@@ -11,29 +11,23 @@
 #include <tuple>
 
 #include "ray.hpp"
+#include "reduce.hpp"
 
 namespace nbt {
 
-// Consecutive workgroup ids are dealt round-robin to the 8 XCDs.  Remapping
-// gives each XCD a contiguous range of logical workgroups, i.e. of
-// perspectives, so perspectives that look at the same region share one L2.
-__device__ __forceinline__ uint32_t xcd_logical(uint32_t bid, uint32_t nb) {
+// Consecutive workgroup ids are dealt round-robin to the 8 XCDs, so the
+// workgroups of one perspective would land on different L2s.  With a chunk
+// C > 0 each XCD instead receives runs of C consecutive logical workgroups
+// (runs interleaved across XCDs in launch order, so all XCDs still progress
+// through the perspectives together); the incomplete last round keeps the
+// identity order.  The mapping is a bijection on [0, nb).
+__device__ __forceinline__ uint32_t xcd_logical(uint32_t bid, uint32_t nb, uint32_t chunk) {
     constexpr uint32_t kXcd = 8;
+    const uint32_t round = kXcd * chunk;
+    const uint32_t full = (nb / round) * round;
+    if (bid >= full) return bid;
     const uint32_t xcd = bid % kXcd, slot = bid / kXcd;
-    const uint32_t full = nb / kXcd, rem = nb % kXcd;
-    return xcd * full + (xcd < rem ? xcd : rem) + slot;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-__device__ __forceinline__ unsigned int wave_sum_u32(unsigned int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return ((slot / chunk) * kXcd + xcd) * chunk + slot % chunk;
 }
 
 template <int WAVES, int DEPTH>
@@ -41,7 +35,7 @@ __global__ __launch_bounds__(WAVES * 64) void ig_viewpoints_kernel(
     DevMap m, CamParams c, const float* __restrict__ poses, uint32_t groups, uint32_t tiles_x,
     uint32_t tiles, int tw_log2, int tpw, int remap, float* __restrict__ ig_out,
     unsigned long long* __restrict__ steps_out, VpAccum* __restrict__ ws) {
-    const uint32_t bid = remap ? xcd_logical(blockIdx.x, gridDim.x) : blockIdx.x;
+    const uint32_t bid = remap > 0 ? xcd_logical(blockIdx.x, gridDim.x, (uint32_t)remap) : blockIdx.x;
     const uint32_t vp = bid / groups;
     const uint32_t g = bid - vp * groups;
 

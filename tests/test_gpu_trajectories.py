@@ -1,0 +1,154 @@
+"""GPU parity of the per-trajectory union IG against the CPU oracle (through the C ABI).
+
+Bar: |U|, per-state counts and total visits bit-exact; union IG within 1e-5
+relative.  The LDS and the global-memory bitset paths are both exercised.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import look_at, make_config, scene_spheres, trajectories_walk
+from workloads.configs import Camera
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def nbt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2503_22588_amd as nbt
+    return nbt
+
+
+@pytest.fixture(scope="module")
+def ctx(nbt):
+    c = nbt.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _run(nbt, m, cam, traj):
+    import torch
+    ig, counts, visits = nbt.eval_trajectories(m, cam, _dev(traj))
+    torch.cuda.synchronize()
+    return ig.cpu().numpy(), counts.cpu().numpy().astype(np.uint32), visits.cpu().numpy().view(np.uint64)
+
+
+def _check(got, ref):
+    ig, counts, visits = got
+    ig_ref, counts_ref, visits_ref = ref
+    assert np.array_equal(counts, counts_ref), (np.argwhere(counts != counts_ref)[:5], counts[:3], counts_ref[:3])
+    assert np.array_equal(visits, visits_ref)
+    nan = np.isnan(ig_ref)
+    assert np.array_equal(np.isnan(ig), nan)
+    rel = np.abs(ig[~nan] - ig_ref[~nan]) / np.maximum(np.abs(ig_ref[~nan]), 1e-30)
+    assert rel.size == 0 or rel.max() <= 1e-5, rel.max()
+
+
+@pytest.fixture(scope="module")
+def small(nbt, ctx):
+    sc = scene_spheres(n=(64, 56, 60), voxel=0.05, n_spheres=40, seed=401, origin=(0.1, -0.3, 0.2))
+    cam = Camera(41, 29, 60, 45, 1.2)
+    traj = trajectories_walk(sc.poi, 10, 5, seed=402)
+    m = nbt.Map(ctx, sc.P, sc.voxel, sc.origin)
+    ref = oracle.eval_trajectories(sc, cam, traj)
+    return sc, cam, traj, m, ref
+
+
+def test_small_lds_path(nbt, ctx, small):
+    sc, cam, traj, m, ref = small
+    _note(f"trajectories: LDS path, context {ctx.info()}")
+    ctx.set_lds_budget(0)
+    _check(_run(nbt, m, cam, traj), ref)
+    assert ref[1][:, 0].min() > 1000
+
+
+def test_small_global_and_mixed_paths(nbt, ctx, small):
+    sc, cam, traj, m, ref = small
+    _note("trajectories: global path")
+    try:
+        ctx.set_lds_budget(64)                # every box is larger: all global
+        _check(_run(nbt, m, cam, traj), ref)
+        ctx.set_lds_budget(30 * 1024)         # some fit, some do not
+        _check(_run(nbt, m, cam, traj), ref)
+    finally:
+        ctx.set_lds_budget(0)
+
+
+def test_single_pose_equals_distinct_voxels(nbt, ctx, small):
+    import torch
+    sc, cam, traj, m, _ = small
+    one = traj[:3, :1]
+    ig, counts, visits = _run(nbt, m, cam, one)
+    d = nbt.trace_rays(m, cam, _dev(one[:, 0]))
+    torch.cuda.synchronize()
+    for t in range(3):
+        paths = set()
+        for k in range(cam.rays):
+            paths.update(int(v) for v in oracle.cast_ray(sc, cam, one[t, 0], k % cam.width, k // cam.width)["path"])
+        assert counts[t, 0] == len(paths)
+        assert visits[t] == int(d["steps"][t].sum().item())
+
+
+def test_duplicates_and_permutation(nbt, ctx, small):
+    sc, cam, traj, m, _ = small
+    base = _run(nbt, m, cam, traj)
+    perm = _run(nbt, m, cam, traj[:, ::-1].copy())
+    dup = _run(nbt, m, cam, np.concatenate([traj, traj[:, :2]], axis=1))
+    assert np.array_equal(base[1], perm[1]) and np.array_equal(base[1], dup[1])
+    assert np.array_equal(base[0], perm[0]) and np.array_equal(base[0], dup[0])
+    assert np.all(dup[2] > base[2])
+
+
+def test_edge_cases(nbt, ctx, small):
+    import torch
+    sc, cam, traj, m, _ = small
+    _note("trajectories: edge cases")
+    bad = traj[:3].copy()
+    bad[1, 2, 0] = np.inf
+    out = _run(nbt, m, cam, bad)
+    ref = oracle.eval_trajectories(sc, cam, bad)
+    _check(out, ref)
+    assert math.isnan(out[0][1]) and not math.isnan(out[0][0])
+    # empty trajectories (no poses) and a no-op call
+    empty = np.zeros((2, 0, 12), np.float32)
+    ig, counts, visits = nbt.eval_trajectories(m, cam, torch.zeros((2, 0, 12), device="cuda"))
+    torch.cuda.synchronize()
+    assert np.all(counts.cpu().numpy() == 0) and np.all(ig.cpu().numpy() == 0) and np.all(visits.cpu().numpy() == 0)
+    ig, counts, visits = nbt.eval_trajectories(m, cam, torch.zeros((0, 4, 12), device="cuda"))
+    assert ig.numel() == 0
+    # a trajectory that looks away from the map sees nothing
+    away = look_at(np.array([[-5.0, -5.0, -5.0]] * 2), np.array([-9.0, -9.0, -9.0]))[None]
+    out = _run(nbt, m, cam, away)
+    assert np.all(out[1] == 0) and out[0][0] == 0.0
+
+
+def test_cfg4_full_size_sampled(nbt, ctx):
+    """Config 4 at its real size (4096 trajectories x 24 poses x 128x96 rays on a 256^3 map):
+    all trajectories on the GPU, the oracle on a seeded sample."""
+    w = make_config(4)
+    sc, cam, traj = w.maps[0], w.camera, w.poses[0]
+    _note(f"cfg4 full size: {traj.shape}")
+    m = nbt.Map(ctx, sc.P, sc.voxel, sc.origin)
+    ig, counts, visits = _run(nbt, m, cam, traj)
+    rng = np.random.default_rng(44)
+    pick = np.sort(rng.choice(traj.shape[0], size=2, replace=False))
+    ref = oracle.eval_trajectories(sc, cam, traj[pick])
+    _check((ig[pick], counts[pick], visits[pick]), ref)
+    assert np.all(counts[:, 0] == counts[:, 1:].sum(axis=1))
+    assert np.all(counts[:, 0] > 0)
