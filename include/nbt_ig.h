@@ -78,6 +78,7 @@ enum { NBT_IG_OCCUPIED = 1, NBT_IG_FREE = 2, NBT_IG_UNKNOWN = 3 };
 
 typedef struct nbt_ig_ctx nbt_ig_ctx;
 typedef struct nbt_ig_map nbt_ig_map;
+typedef struct nbt_ig_batch nbt_ig_batch;
 
 /* The far-plane endpoint grid of one perspective (Sec. III, endpoint calculation). */
 typedef struct {
@@ -212,6 +213,51 @@ typedef struct {
 
 int nbt_ig_ctx_set_launch(nbt_ig_ctx* ctx, const nbt_ig_launch* launch);
 int nbt_ig_ctx_get_launch(const nbt_ig_ctx* ctx, nbt_ig_launch* launch);
+
+/* ---- batched evaluation over many maps -------------------------------------------
+ * The per-perspective IG of nbt_ig_eval_viewpoints for many maps of uneven
+ * size and uneven perspective counts in ONE persistent launch: workgroups
+ * (as many as fit on the device at once) pull (perspective, ray-slice) items
+ * in map-major order from a device work queue until it is empty.
+ *
+ * nbt_ig_batch_create: `maps` (HOST array of n_maps handles of this context)
+ * and the camera are fixed for the batch; max_total_viewpoints bounds the
+ * perspectives of one run.  The launch shape starts as the context's.
+ *
+ * nbt_ig_batch_run: vp_offsets is a DEVICE CSR uint32 [n_maps+1] (perspectives
+ * of map k are vp_offsets[k] .. vp_offsets[k+1]-1, non-decreasing,
+ * vp_offsets[0] = 0); poses float32 [total][12], ig_out float32 [total],
+ * steps_out uint64 [total] or NULL, where total = vp_offsets[n_maps] (runs
+ * clamp it to max_total_viewpoints).  The offsets are read on the device, so
+ * the same batch can run different counts without host synchronisation.  The
+ * first run (and any run with different buffer pointers) builds a hipGraph of
+ * the queue reset and the persistent kernel; later runs replay it.  Results
+ * equal nbt_ig_eval_viewpoints on each map (step counts exactly).  Runs of one
+ * batch must be ordered on one stream.
+ */
+int nbt_ig_batch_create(nbt_ig_ctx* ctx, const nbt_ig_map* const* maps, uint32_t n_maps,
+                        const nbt_ig_camera* cam, uint32_t max_total_viewpoints, nbt_ig_batch** out);
+void nbt_ig_batch_destroy(nbt_ig_batch* batch);  /* NULL is a no-op; caller syncs first */
+int nbt_ig_batch_run(nbt_ig_batch* batch, const uint32_t* vp_offsets, const float* poses, float* ig_out,
+                     uint64_t* steps_out, void* stream);
+/* xcd_remap is ignored by the persistent launch.  persistent_groups (HOST, may be
+ * NULL) receives the number of workgroups launched. */
+int nbt_ig_batch_set_launch(nbt_ig_batch* batch, const nbt_ig_launch* launch);
+int nbt_ig_batch_get_launch(const nbt_ig_batch* batch, nbt_ig_launch* launch, uint32_t* persistent_groups);
+
+/* ---- autotuning ----------------------------------------------------------------------
+ * Time candidate launch shapes (coordinate search over waves_per_group,
+ * tile_w_log2, tiles_per_wave and pipeline_depth, two passes) on the given
+ * inputs, keep the fastest in the context (or batch) and report it with its
+ * mean time per launch in milliseconds (HOST outputs).  Outputs are written
+ * as by the evaluation calls.  Synchronises `stream`.
+ */
+int nbt_ig_autotune_viewpoints(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                               uint32_t n, float* ig_out, uint64_t* steps_out, void* stream,
+                               nbt_ig_launch* best, float* best_ms);
+int nbt_ig_batch_autotune(nbt_ig_batch* batch, const uint32_t* vp_offsets, const float* poses,
+                          float* ig_out, uint64_t* steps_out, void* stream, nbt_ig_launch* best,
+                          float* best_ms);
 
 /* ---- helpers ------------------------------------------------------------------- */
 

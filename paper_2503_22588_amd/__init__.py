@@ -7,13 +7,14 @@ package fails when the library has not been built.
 
 from . import binding
 from .binding import (
-    NbtError, Context, Map, CameraT, camera, camera_from_grid,
+    NbtError, Context, Map, Batch, CameraT, camera, camera_from_grid, autotune_viewpoints,
     eval_viewpoints, eval_trajectories, trace_rays, trace_paths,
     RAY_MISS, RAY_HIT, RAY_END, RAY_EXIT, RAY_INVALID,
 )
 
 __all__ = [
-    "binding", "NbtError", "Context", "Map", "CameraT", "camera", "camera_from_grid",
+    "binding", "NbtError", "Context", "Map", "Batch", "CameraT", "camera", "camera_from_grid",
+    "autotune_viewpoints",
     "eval_viewpoints", "eval_trajectories", "trace_rays", "trace_paths",
     "RAY_MISS", "RAY_HIT", "RAY_END", "RAY_EXIT", "RAY_INVALID",
 ]

@@ -78,6 +78,14 @@ _sig("nbt_ig_trace_rays", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp)
 _sig("nbt_ig_trace_paths", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _u32, _u32, _vp, _vp, _vp)
 _sig("nbt_ig_ctx_set_launch", C.c_int, _vp, C.POINTER(LaunchT))
 _sig("nbt_ig_ctx_get_launch", C.c_int, _vp, C.POINTER(LaunchT))
+_sig("nbt_ig_batch_create", C.c_int, _vp, C.POINTER(_vp), _u32, C.POINTER(CameraT), _u32, C.POINTER(_vp))
+_sig("nbt_ig_batch_destroy", None, _vp)
+_sig("nbt_ig_batch_run", C.c_int, _vp, _vp, _vp, _vp, _vp, _vp)
+_sig("nbt_ig_batch_set_launch", C.c_int, _vp, C.POINTER(LaunchT))
+_sig("nbt_ig_batch_get_launch", C.c_int, _vp, C.POINTER(LaunchT), C.POINTER(_u32))
+_sig("nbt_ig_autotune_viewpoints", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp, _vp,
+     C.POINTER(LaunchT), C.POINTER(C.c_float))
+_sig("nbt_ig_batch_autotune", C.c_int, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(LaunchT), C.POINTER(C.c_float))
 _sig("nbt_ig_camera_from_grid", C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
      C.POINTER(CameraT))
 
@@ -305,3 +313,77 @@ def trace_paths(m: Map, cam, poses, rays_sel, max_len, stream=None):
                                    poses.shape[0], _dev_ptr(sel, None, "rays"), count, int(max_len),
                                    _dev_ptr(lin, None, "lin"), _dev_ptr(ln, None, "len"), _stream(stream)))
     return lin, ln
+
+
+def _launch_dict(l):
+    return {"waves_per_group": l.waves_per_group, "tile_w_log2": l.tile_w_log2,
+            "tiles_per_wave": l.tiles_per_wave, "xcd_remap": l.xcd_remap,
+            "pipeline_depth": l.pipeline_depth}
+
+
+class Batch:
+    """Many maps, one persistent hipGraph-launched evaluation (nbt_ig_batch)."""
+
+    def __init__(self, ctx: Context, maps, cam, max_total_viewpoints: int):
+        arr = (_vp * len(maps))(*[m.handle for m in maps])
+        h = _vp()
+        self._cam = camera(cam)
+        _check(_lib.nbt_ig_batch_create(ctx.handle, arr, len(maps), C.byref(self._cam),
+                                        int(max_total_viewpoints), C.byref(h)))
+        self.handle = h
+        self.maps = list(maps)          # keep the maps alive
+        self.ctx = ctx
+
+    def run(self, vp_offsets, poses, ig_out, steps_out=None, stream=None):
+        torch = _torch()
+        _check(_lib.nbt_ig_batch_run(self.handle, _dev_ptr(vp_offsets, torch.int32, "vp_offsets"),
+                                     _dev_ptr(poses, torch.float32, "poses"),
+                                     _dev_ptr(ig_out, torch.float32, "ig_out"),
+                                     _dev_ptr(steps_out, torch.int64, "steps_out"), _stream(stream)))
+
+    def set_launch(self, waves_per_group=4, tile_w_log2=3, tiles_per_wave=16, pipeline_depth=0):
+        _check(_lib.nbt_ig_batch_set_launch(self.handle, C.byref(LaunchT(waves_per_group, tile_w_log2,
+                                                                          tiles_per_wave, 0, pipeline_depth))))
+
+    def get_launch(self):
+        l, g = LaunchT(), _u32()
+        _check(_lib.nbt_ig_batch_get_launch(self.handle, C.byref(l), C.byref(g)))
+        d = _launch_dict(l)
+        d["persistent_groups"] = g.value
+        return d
+
+    def autotune(self, vp_offsets, poses, ig_out, steps_out=None, stream=None):
+        torch = _torch()
+        l, ms = LaunchT(), C.c_float()
+        _check(_lib.nbt_ig_batch_autotune(self.handle, _dev_ptr(vp_offsets, torch.int32, "vp_offsets"),
+                                          _dev_ptr(poses, torch.float32, "poses"),
+                                          _dev_ptr(ig_out, torch.float32, "ig_out"),
+                                          _dev_ptr(steps_out, torch.int64, "steps_out"), _stream(stream),
+                                          C.byref(l), C.byref(ms)))
+        return _launch_dict(l), ms.value
+
+    def close(self):
+        if self.handle:
+            _lib.nbt_ig_batch_destroy(self.handle)
+            self.handle = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune_viewpoints(m: Map, cam, poses, ig_out=None, steps_out=None, stream=None):
+    """Pick the fastest launch shape for these inputs; the context keeps it."""
+    torch = _torch()
+    n = poses.shape[0]
+    if ig_out is None:
+        ig_out = torch.empty(n, dtype=torch.float32, device=poses.device)
+    cm = camera(cam)
+    l, ms = LaunchT(), C.c_float()
+    _check(_lib.nbt_ig_autotune_viewpoints(m.handle, C.byref(cm), _dev_ptr(poses, torch.float32, "poses"), n,
+                                           _dev_ptr(ig_out, torch.float32, "ig_out"),
+                                           _dev_ptr(steps_out, torch.int64, "steps_out"), _stream(stream),
+                                           C.byref(l), C.byref(ms)))
+    return _launch_dict(l), ms.value

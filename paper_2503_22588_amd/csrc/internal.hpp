@@ -98,6 +98,10 @@ hipError_t launch_traj_union(bool global, const DevMap& m, const CamParams& c, c
                              const uint32_t* over_list, uint32_t* gbits, float* ig_union,
                              uint32_t* counts, unsigned long long* visits, hipStream_t s);
 
+// Kernel entry points of the persistent batched launch (for graph nodes).
+const void* batch_kernel_ptr(int waves, int depth);
+const void* batch_reset_ptr();
+
 // Number of workgroups a perspective is split into for a launch shape.
 inline uint32_t vp_groups(const CamParams& c, const VpLaunch& L) {
     const int tw = 1 << L.tile_w_log2, th = 64 >> L.tile_w_log2;

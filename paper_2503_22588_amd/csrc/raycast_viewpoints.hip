@@ -30,18 +30,20 @@ __device__ __forceinline__ uint32_t xcd_logical(uint32_t bid, uint32_t nb, uint3
     return ((slot / chunk) * kXcd + xcd) * chunk + slot % chunk;
 }
 
+// The rays of workgroup-slice g of perspective vp: WAVES waves walk their
+// tiles, then the block's sum is written (groups == 1) or combined with the
+// other slices of the perspective (last slice writes).  Called uniformly by
+// the whole block.
 template <int WAVES, int DEPTH>
-__global__ __launch_bounds__(WAVES * 64) void ig_viewpoints_kernel(
-    DevMap m, CamParams c, const float* __restrict__ poses, uint32_t groups, uint32_t tiles_x,
-    uint32_t tiles, int tw_log2, int tpw, int remap, float* __restrict__ ig_out,
-    unsigned long long* __restrict__ steps_out, VpAccum* __restrict__ ws) {
-    const uint32_t bid = remap > 0 ? xcd_logical(blockIdx.x, gridDim.x, (uint32_t)remap) : blockIdx.x;
-    const uint32_t vp = bid / groups;
-    const uint32_t g = bid - vp * groups;
-
+__device__ __forceinline__ void vp_group(const DevMap& m, const CamParams& c,
+                                         const float* __restrict__ pp, uint32_t vp, uint32_t g,
+                                         uint32_t groups, uint32_t tiles_x, uint32_t tiles,
+                                         int tw_log2, int tpw, float* __restrict__ ig_out,
+                                         unsigned long long* __restrict__ steps_out,
+                                         VpAccum* __restrict__ ws) {
     float pose[12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) pose[k] = poses[12 * (size_t)vp + k];
+    for (int k = 0; k < 12; ++k) pose[k] = pp[k];
 
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -67,9 +69,9 @@ __global__ __launch_bounds__(WAVES * 64) void ig_viewpoints_kernel(
                     walk_ray<false>(m, rs, ray, acc, steps, [](int, int, int) {});
                 else
                     walk_ray_pipelined<DEPTH>(m, rs, ray, acc, steps);
-            }
-            else if (st == kRayInvalid)
+            } else if (st == kRayInvalid) {
                 invalid = true;
+            }
         }
     }
 
@@ -119,6 +121,64 @@ __global__ __launch_bounds__(WAVES * 64) void ig_viewpoints_kernel(
         if (steps_out) steps_out[vp] = stp;
     }
 }
+
+template <int WAVES, int DEPTH>
+__global__ __launch_bounds__(WAVES * 64) void ig_viewpoints_kernel(
+    DevMap m, CamParams c, const float* __restrict__ poses, uint32_t groups, uint32_t tiles_x,
+    uint32_t tiles, int tw_log2, int tpw, int remap, float* __restrict__ ig_out,
+    unsigned long long* __restrict__ steps_out, VpAccum* __restrict__ ws) {
+    const uint32_t bid = remap > 0 ? xcd_logical(blockIdx.x, gridDim.x, (uint32_t)remap) : blockIdx.x;
+    const uint32_t vp = bid / groups;
+    const uint32_t g = bid - vp * groups;
+    vp_group<WAVES, DEPTH>(m, c, poses + 12 * (size_t)vp, vp, g, groups, tiles_x, tiles, tw_log2, tpw,
+                           ig_out, steps_out, ws);
+}
+
+// Persistent batched launch: many maps, a CSR of perspectives per map
+// (offsets[k]..offsets[k+1]).  Work items are (perspective, slice) pairs in
+// map-major order; each workgroup pops items from an atomic counter until
+// the queue is empty, so uneven maps and perspective counts balance across
+// the chip and co-resident workgroups share one map in L2.
+template <int WAVES, int DEPTH>
+__global__ __launch_bounds__(WAVES * 64) void ig_batch_kernel(
+    const DevMap* __restrict__ maps, uint32_t n_maps, const uint32_t* __restrict__ offsets,
+    uint32_t capacity, CamParams c, const float* __restrict__ poses, uint32_t groups,
+    uint32_t tiles_x, uint32_t tiles, int tw_log2, int tpw, unsigned int* __restrict__ queue,
+    float* __restrict__ ig_out, unsigned long long* __restrict__ steps_out,
+    VpAccum* __restrict__ ws) {
+    __shared__ uint32_t s_item, s_map;
+    uint32_t total = offsets[n_maps];
+    total = total < capacity ? total : capacity;
+    const uint64_t items = (uint64_t)total * groups;
+    for (;;) {
+        __syncthreads();                    // previous item's reductions are done
+        if (threadIdx.x == 0) {
+            const uint32_t it = atomicAdd(queue, 1u);
+            uint32_t mi = 0;
+            if (it < items) {
+                const uint32_t vp = it / groups;
+                uint32_t lo = 0, hi = n_maps;          // largest k with offsets[k] <= vp
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) / 2;
+                    if (offsets[mid] <= vp) lo = mid; else hi = mid;
+                }
+                mi = lo;
+            }
+            s_item = it;
+            s_map = mi;
+        }
+        __syncthreads();
+        const uint32_t it = s_item;
+        if (it >= items) return;
+        const uint32_t vp = it / groups;
+        const uint32_t g = it - vp * groups;
+        const DevMap m = maps[s_map];
+        vp_group<WAVES, DEPTH>(m, c, poses + 12 * (size_t)vp, vp, g, groups, tiles_x, tiles, tw_log2,
+                               tpw, ig_out, steps_out, ws);
+    }
+}
+
+__global__ void batch_reset_kernel(unsigned int* queue) { *queue = 0u; }
 
 // Parity mode: one thread per ray, full record per ray.
 __global__ __launch_bounds__(256) void trace_rays_kernel(DevMap m, CamParams c,
@@ -231,6 +291,18 @@ hipError_t launch_eval_viewpoints(const DevMap& m, const CamParams& c, const flo
 #undef NBT_VP_DEPTHS
     return hipGetLastError();
 }
+
+const void* batch_kernel_ptr(int waves, int depth) {
+#define NBT_BK(W, D) if (waves == W && depth == D) return (const void*)ig_batch_kernel<W, D>;
+    NBT_BK(1, 1) NBT_BK(1, 2) NBT_BK(1, 4) NBT_BK(1, 8)
+    NBT_BK(2, 1) NBT_BK(2, 2) NBT_BK(2, 4) NBT_BK(2, 8)
+    NBT_BK(4, 1) NBT_BK(4, 2) NBT_BK(4, 4) NBT_BK(4, 8)
+    NBT_BK(8, 1) NBT_BK(8, 2) NBT_BK(8, 4) NBT_BK(8, 8)
+#undef NBT_BK
+    return nullptr;
+}
+
+const void* batch_reset_ptr() { return (const void*)batch_reset_kernel; }
 
 hipError_t launch_trace_rays(const DevMap& m, const CamParams& c, const float* poses, uint32_t n,
                              nbt_ig_ray_digest* out, hipStream_t s) {

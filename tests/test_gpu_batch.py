@@ -1,0 +1,181 @@
+"""GPU tests of the persistent, hipGraph-launched batched evaluation.
+
+Bar: per-perspective voxel steps equal the single-map path and the oracle
+exactly; IG equals the single-map path bit for bit in the same launch shape
+and the oracle within 1e-5 relative.  Every graph replay is checked.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import make_config, poses_sphere, scene_spheres
+from workloads.configs import Camera
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def nbt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2503_22588_amd as nbt
+    return nbt
+
+
+@pytest.fixture(scope="module")
+def ctx(nbt):
+    c = nbt.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def uneven(nbt, ctx):
+    dims = [(24, 24, 24), (40, 32, 28), (64, 64, 64), (17, 33, 9), (48, 48, 48), (30, 20, 50)]
+    counts = [5, 0, 31, 1, 13, 9]
+    scenes = [scene_spheres(n=d, voxel=0.05, n_spheres=8 + 3 * k, seed=500 + k) for k, d in enumerate(dims)]
+    cam = Camera(37, 29, 60, 45, 2.0)
+    poses = [poses_sphere(s.poi, 0.7, c, seed=600 + k) if c else np.zeros((0, 12), np.float32)
+             for k, (s, c) in enumerate(zip(scenes, counts))]
+    maps = [nbt.Map(ctx, s.P, s.voxel, s.origin) for s in scenes]
+    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    allp = np.concatenate(poses, axis=0)
+    return scenes, cam, poses, maps, offsets, allp
+
+
+def _single(nbt, maps, cam, poses):
+    import torch
+    igs, sts = [], []
+    for m, p in zip(maps, poses):
+        if p.shape[0] == 0:
+            continue
+        ig, st = nbt.eval_viewpoints(m, cam, _dev(p))
+        torch.cuda.synchronize()
+        igs.append(ig.cpu().numpy())
+        sts.append(st.cpu().numpy())
+    return np.concatenate(igs), np.concatenate(sts)
+
+
+def test_batch_matches_single_map_and_oracle(nbt, ctx, uneven):
+    import torch
+    scenes, cam, poses, maps, offsets, allp = uneven
+    _note("batch: uneven maps")
+    b = nbt.Batch(ctx, maps, cam, 256)
+    off, dp = _dev(offsets), _dev(allp)
+    ig = torch.empty(allp.shape[0], device="cuda")
+    st = torch.empty(allp.shape[0], dtype=torch.int64, device="cuda")
+    ig_single, st_single = _single(nbt, maps, cam, poses)
+    for rep in range(3):                      # first run builds the graph, the others replay it
+        ig.fill_(-1.0)
+        st.fill_(-1)
+        b.run(off, dp, ig, st)
+        torch.cuda.synchronize()
+        assert np.array_equal(st.cpu().numpy(), st_single), rep
+        assert np.array_equal(ig.cpu().numpy(), ig_single), rep
+        _ = torch.ones(1000, device="cuda").sum().item()   # eager work between replays
+    ref_ig, ref_st = [], []
+    for s, p in zip(scenes, poses):
+        if p.shape[0]:
+            a, c = oracle.eval_viewpoints(s, cam, p)
+            ref_ig.append(a)
+            ref_st.append(c)
+    ref_ig, ref_st = np.concatenate(ref_ig), np.concatenate(ref_st)
+    assert np.array_equal(st_single.view(np.uint64), ref_st)
+    rel = np.abs(ig_single - ref_ig) / np.maximum(ref_ig, 1e-30)
+    assert rel.max() <= 1e-5
+    b.close()
+
+
+def test_batch_counts_change_on_device(nbt, ctx, uneven):
+    """New perspective counts written into the same offsets buffer are picked up by a replay."""
+    import torch
+    scenes, cam, poses, maps, offsets, allp = uneven
+    b = nbt.Batch(ctx, maps, cam, 256)
+    off, dp = _dev(offsets), _dev(allp)
+    ig = torch.empty(allp.shape[0], device="cuda")
+    st = torch.empty(allp.shape[0], dtype=torch.int64, device="cuda")
+    b.run(off, dp, ig, st)
+    torch.cuda.synchronize()
+    full_ig, full_st = ig.cpu().numpy().copy(), st.cpu().numpy().copy()
+    # shrink: keep the first perspectives of each map only (same poses buffer layout per map start)
+    new_counts = [min(c, 2) for c in np.diff(offsets)]
+    sub = np.concatenate([p[:c] for p, c in zip(poses, new_counts)], axis=0)
+    new_off = np.concatenate([[0], np.cumsum(new_counts)]).astype(np.int32)
+    dp[: sub.shape[0]].copy_(_dev(sub))
+    off.copy_(_dev(new_off))
+    st.fill_(-7)
+    b.run(off, dp, ig, st)
+    torch.cuda.synchronize()
+    got_st = st.cpu().numpy()
+    exp = np.concatenate([full_st[offsets[k]:offsets[k] + c] for k, c in enumerate(new_counts)])
+    assert np.array_equal(got_st[: sub.shape[0]], exp)
+    assert np.all(got_st[sub.shape[0]:] == -7)
+    # zero perspectives: nothing is written
+    off.zero_()
+    st.fill_(-9)
+    b.run(off, dp, ig, st)
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == -9)
+    b.close()
+
+
+def test_batch_launch_shapes_and_autotune(nbt, ctx, uneven):
+    import torch
+    scenes, cam, poses, maps, offsets, allp = uneven
+    _note("batch: shapes + autotune")
+    b = nbt.Batch(ctx, maps, cam, 256)
+    off, dp = _dev(offsets), _dev(allp)
+    ig = torch.empty(allp.shape[0], device="cuda")
+    st = torch.empty(allp.shape[0], dtype=torch.int64, device="cuda")
+    _, st_single = _single(nbt, maps, cam, poses)
+    for shape in [(1, 3, 1, 1), (8, 3, 2, 8), (2, 4, 16, 2), (4, 0, 3, 4)]:
+        b.set_launch(*shape)
+        b.run(off, dp, ig, st)
+        torch.cuda.synchronize()
+        assert np.array_equal(st.cpu().numpy(), st_single), shape
+    best, ms = b.autotune(off, dp, ig, st)
+    assert ms > 0 and best["waves_per_group"] in (2, 4, 8)
+    b.run(off, dp, ig, st)
+    torch.cuda.synchronize()
+    assert np.array_equal(st.cpu().numpy(), st_single)
+    b.close()
+
+
+def test_cfg3_full_size(nbt, ctx):
+    """Config 3 at its real size: 64 maps of 64..256^3 voxels, ~31k perspectives."""
+    import torch
+    w = make_config(3)
+    cam = w.camera
+    _note(f"cfg3: {len(w.maps)} maps, {w.n_viewpoints} perspectives")
+    maps = [nbt.Map(ctx, s.P, s.voxel, s.origin) for s in w.maps]
+    counts = [p.shape[0] for p in w.poses]
+    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    allp = np.concatenate(w.poses, axis=0)
+    b = nbt.Batch(ctx, maps, cam, allp.shape[0])
+    off, dp = _dev(offsets), _dev(allp)
+    ig = torch.empty(allp.shape[0], device="cuda")
+    st = torch.empty(allp.shape[0], dtype=torch.int64, device="cuda")
+    b.run(off, dp, ig, st)
+    torch.cuda.synchronize()
+    ig, st = ig.cpu().numpy(), st.cpu().numpy()
+    ig_single, st_single = _single(nbt, maps, cam, w.poses)
+    assert np.array_equal(st, st_single) and np.array_equal(ig, ig_single)
+    rng = np.random.default_rng(33)
+    for k in rng.choice(len(w.maps), size=3, replace=False):
+        pick = rng.choice(counts[k], size=min(3, counts[k]), replace=False)
+        a, c = oracle.eval_viewpoints(w.maps[k], cam, w.poses[k][pick])
+        g = offsets[k] + pick
+        assert np.array_equal(st[g].view(np.uint64), c)
+        assert np.max(np.abs(ig[g] - a) / np.maximum(a, 1e-30)) <= 1e-5
+    b.close()
