@@ -62,6 +62,70 @@ def cpu_baseline(scene, cam, poses, budget_s):
     }
 
 
+def _timed(fn, reps, stream):
+    """Mean milliseconds of fn() over reps launches (HIP events on `stream`)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def extra_trajectories(nbt, ctx, reps):
+    """Trajectory IG: 256^3 sphere map, 4096 trajectories x 24 poses, 128x96 rays."""
+    import numpy as np
+    import torch
+    from workloads import make_config
+    w = make_config(4)
+    sc, cam, traj = w.maps[0], w.camera, w.poses[0]
+    m = nbt.Map(ctx, sc.P, sc.voxel, sc.origin)
+    dt = torch.from_numpy(traj).cuda()
+    out = {}
+
+    def run():
+        out["r"] = nbt.eval_trajectories(m, cam, dt)
+
+    ms = _timed(run, reps, torch.cuda.current_stream())
+    ig, counts, visits = out["r"]
+    vis = int(visits.cpu().numpy().view(np.uint64).sum())
+    rays = traj.shape[0] * traj.shape[1] * cam.width * cam.height
+    return {"workload": "256^3 map (5 cm, 1280 spheres), 4096 trajectories x 24 poses, 128x96 rays",
+            "ms_per_launch": ms, "trajectory_evals_per_s": traj.shape[0] / (ms * 1e-3),
+            "rays_per_s": rays / (ms * 1e-3), "voxel_steps_per_s": vis / (ms * 1e-3),
+            "mean_unique_voxels": float(counts[:, 0].float().mean().item()),
+            "note": "includes the box pre-pass and its one host synchronisation"}
+
+
+def extra_batch(nbt, ctx, reps):
+    """Batched: 64 maps of {64..256}^3, log-uniform 16-2048 perspectives each, one graph launch."""
+    import numpy as np
+    import torch
+    from workloads import make_config
+    w = make_config(3)
+    maps = [nbt.Map(ctx, s.P, s.voxel, s.origin) for s in w.maps]
+    counts = [p.shape[0] for p in w.poses]
+    offsets = torch.from_numpy(np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)).cuda()
+    allp = torch.from_numpy(np.concatenate(w.poses, axis=0)).cuda()
+    n = allp.shape[0]
+    ig = torch.empty(n, device="cuda")
+    st = torch.empty(n, dtype=torch.int64, device="cuda")
+    b = nbt.Batch(ctx, maps, w.camera, n)
+    best, _ = b.autotune(offsets, allp, ig, st)
+    ms = _timed(lambda: b.run(offsets, allp, ig, st), reps, torch.cuda.current_stream())
+    steps = int(st.cpu().numpy().view(np.uint64).sum())
+    rays = n * w.camera.width * w.camera.height
+    res = {"workload": f"64 maps (sizes in {{64,96,128,192,256}}^3, 5 cm), {n} perspectives, 64x48 rays",
+           "batch_latency_ms": ms, "viewpoint_evals_per_s": n / (ms * 1e-3), "rays_per_s": rays / (ms * 1e-3),
+           "voxel_steps_per_s": steps / (ms * 1e-3), "launch": b.get_launch()}
+    b.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +135,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default=None,
                     help="waves,tile_w_log2,tiles_per_wave,xcd_remap,pipeline_depth")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the trajectory and batched measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -184,6 +250,11 @@ def main():
             "traffic": None,
         },
     }
+    if not args.no_extras:
+        _log("measuring trajectory IG (config 4) ...")
+        result["trajectories"] = extra_trajectories(nbt, ctx, reps=3)
+        _log("measuring the batched launch (config 3) ...")
+        result["batched"] = extra_batch(nbt, ctx, reps=5)
     if not args.no_cpu_baseline:
         _log("timing the CPU oracle baseline ...")
         result["cpu_baseline"] = cpu_baseline(scene, cam, poses, args.cpu_seconds)
