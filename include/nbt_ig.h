@@ -79,6 +79,7 @@ enum { NBT_IG_OCCUPIED = 1, NBT_IG_FREE = 2, NBT_IG_UNKNOWN = 3 };
 typedef struct nbt_ig_ctx nbt_ig_ctx;
 typedef struct nbt_ig_map nbt_ig_map;
 typedef struct nbt_ig_batch nbt_ig_batch;
+typedef struct nbt_ig_surrogate nbt_ig_surrogate;
 
 /* The far-plane endpoint grid of one perspective (Sec. III, endpoint calculation). */
 typedef struct {
@@ -258,6 +259,52 @@ int nbt_ig_autotune_viewpoints(const nbt_ig_map* map, const nbt_ig_camera* cam, 
 int nbt_ig_batch_autotune(nbt_ig_batch* batch, const uint32_t* vp_offsets, const float* poses,
                           float* ig_out, uint64_t* steps_out, void* stream, nbt_ig_launch* best,
                           float* best_ms);
+
+/* ---- learned IG surrogate ----------------------------------------------------------
+ * A small network trained on this library's own exact IG predicts g_P of a
+ * candidate perspective from (a) a 32^3 x 2 patch around the PoI holding the
+ * fraction of occupied and of unknown voxels per cell and (b) the candidate's
+ * unit direction and distance from the PoI; it prunes candidates so that only
+ * the best few are raycast exactly (Sec. III's g_P stays the judge).
+ * Network: 4 conv3d layers (3^3, stride 2, ReLU; 2-16-32-64-64 channels,
+ * 32^3 -> 2^3) -> 512 features; MLP 516 -> 256 -> 256 -> 1 (ReLU).  Inference
+ * runs in BF16 on MFMA with FP32 accumulation; the pose-independent part of
+ * the first MLP layer is computed once per map.
+ *
+ * weights (HOST, nbytes): "NBTS", uint32 version 1, float extent (patch cube
+ * side, metres), dist_mean, dist_scale, out_scale, 2 reserved uint32, then
+ * little-endian float32: conv1..4 weights [cout][cin][3][3][3] and biases,
+ * fc1 [256][516] + bias, fc2 [256][256] + bias, fc3 [256] + bias.  Patch cells
+ * are f^3 voxels, f = max(1, round(extent / (32 voxel_size))), centred on the
+ * voxel nearest the PoI; voxels outside the map count as neither state.
+ */
+int nbt_ig_surrogate_create(nbt_ig_ctx* ctx, const void* weights, size_t nbytes, nbt_ig_surrogate** out);
+void nbt_ig_surrogate_destroy(nbt_ig_surrogate* s);   /* NULL is a no-op; caller syncs first */
+
+/* pred[i] (DEVICE float32 [n]) = predicted IG of pose i (DEVICE float32 [n][12])
+ * for the PoI `poi` (HOST, 3 floats, world metres).  Calls on one surrogate
+ * must be ordered on one stream (they share its buffers). */
+int nbt_ig_surrogate_predict(nbt_ig_surrogate* s, const nbt_ig_map* map, const float poi[3],
+                             const float* poses, uint32_t n, float* pred, void* stream);
+
+/* Predict all n candidates, keep the k_rescore best predictions (ties to the
+ * lower index), evaluate those exactly (nbt_ig_eval_viewpoints with `cam`),
+ * and return the k best by exact IG: idx_out (DEVICE uint32 [k]) candidate
+ * indices, ig_out (DEVICE float32 [k]) their exact IG, best first (ties to the
+ * lower index).  1 <= k <= k_rescore <= 64, k_rescore <= n <= 2^18. */
+int nbt_ig_surrogate_select(nbt_ig_surrogate* s, const nbt_ig_map* map, const nbt_ig_camera* cam,
+                            const float poi[3], const float* poses, uint32_t n, uint32_t k_rescore,
+                            uint32_t k, uint32_t* idx_out, float* ig_out, void* stream);
+
+/* Intermediate values for verification (DEVICE outputs, either may be NULL):
+ * the patch as float32 [2][32][32][32] (channel, z, y, x) and the 512 trunk
+ * features as float32 (their BF16 values). */
+int nbt_ig_surrogate_features(nbt_ig_surrogate* s, const nbt_ig_map* map, const float poi[3],
+                              float* patch_out, float* features_out, void* stream);
+
+/* The surrogate's input patch for any cube side `extent` (training data):
+ * out DEVICE float32 [2][32][32][32]. */
+int nbt_ig_extract_patch(const nbt_ig_map* map, const float poi[3], float extent, float* out, void* stream);
 
 /* ---- helpers ------------------------------------------------------------------- */
 

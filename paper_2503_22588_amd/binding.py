@@ -86,6 +86,13 @@ _sig("nbt_ig_batch_get_launch", C.c_int, _vp, C.POINTER(LaunchT), C.POINTER(_u32
 _sig("nbt_ig_autotune_viewpoints", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp, _vp,
      C.POINTER(LaunchT), C.POINTER(C.c_float))
 _sig("nbt_ig_batch_autotune", C.c_int, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(LaunchT), C.POINTER(C.c_float))
+_sig("nbt_ig_surrogate_create", C.c_int, _vp, C.c_void_p, C.c_size_t, C.POINTER(_vp))
+_sig("nbt_ig_surrogate_destroy", None, _vp)
+_sig("nbt_ig_surrogate_predict", C.c_int, _vp, _vp, C.POINTER(C.c_float), _vp, _u32, _vp, _vp)
+_sig("nbt_ig_surrogate_select", C.c_int, _vp, _vp, C.POINTER(CameraT), C.POINTER(C.c_float), _vp, _u32, _u32,
+     _u32, _vp, _vp, _vp)
+_sig("nbt_ig_surrogate_features", C.c_int, _vp, _vp, C.POINTER(C.c_float), _vp, _vp, _vp)
+_sig("nbt_ig_extract_patch", C.c_int, _vp, C.POINTER(C.c_float), C.c_float, _vp, _vp)
 _sig("nbt_ig_camera_from_grid", C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
      C.POINTER(CameraT))
 
@@ -387,3 +394,66 @@ def autotune_viewpoints(m: Map, cam, poses, ig_out=None, steps_out=None, stream=
                                            _dev_ptr(steps_out, torch.int64, "steps_out"), _stream(stream),
                                            C.byref(l), C.byref(ms)))
     return _launch_dict(l), ms.value
+
+
+def _poi(poi):
+    return (C.c_float * 3)(*[float(v) for v in poi])
+
+
+def extract_patch(m: Map, poi, extent, stream=None):
+    """Occupied / unknown fractions [2, 32, 32, 32] around the PoI (float32 device tensor)."""
+    torch = _torch()
+    out = torch.empty((2, 32, 32, 32), dtype=torch.float32, device="cuda")
+    _check(_lib.nbt_ig_extract_patch(m.handle, _poi(poi), float(extent), _dev_ptr(out, torch.float32, "out"),
+                                     _stream(stream)))
+    return out
+
+
+class Surrogate:
+    """The learned IG surrogate (nbt_ig_surrogate); `weights` is the packed blob (bytes)."""
+
+    def __init__(self, ctx: Context, weights: bytes):
+        h = _vp()
+        buf = C.create_string_buffer(bytes(weights), len(weights))
+        _check(_lib.nbt_ig_surrogate_create(ctx.handle, C.cast(buf, C.c_void_p), len(weights), C.byref(h)))
+        self.handle = h
+        self.ctx = ctx
+
+    def predict(self, m: Map, poi, poses, pred=None, stream=None):
+        torch = _torch()
+        n = poses.shape[0]
+        if pred is None:
+            pred = torch.empty(n, dtype=torch.float32, device=poses.device)
+        _check(_lib.nbt_ig_surrogate_predict(self.handle, m.handle, _poi(poi), _dev_ptr(poses, torch.float32, "poses"),
+                                             n, _dev_ptr(pred, torch.float32, "pred"), _stream(stream)))
+        return pred
+
+    def select(self, m: Map, cam, poi, poses, k_rescore=64, k=10, stream=None):
+        torch = _torch()
+        idx = torch.empty(k, dtype=torch.int32, device=poses.device)
+        ig = torch.empty(k, dtype=torch.float32, device=poses.device)
+        cm = camera(cam)
+        _check(_lib.nbt_ig_surrogate_select(self.handle, m.handle, C.byref(cm), _poi(poi),
+                                            _dev_ptr(poses, torch.float32, "poses"), poses.shape[0], int(k_rescore),
+                                            int(k), _dev_ptr(idx, None, "idx"), _dev_ptr(ig, torch.float32, "ig"),
+                                            _stream(stream)))
+        return idx, ig
+
+    def features(self, m: Map, poi, stream=None):
+        torch = _torch()
+        patch = torch.empty((2, 32, 32, 32), dtype=torch.float32, device="cuda")
+        feat = torch.empty(512, dtype=torch.float32, device="cuda")
+        _check(_lib.nbt_ig_surrogate_features(self.handle, m.handle, _poi(poi), _dev_ptr(patch, None, "patch"),
+                                              _dev_ptr(feat, None, "feat"), _stream(stream)))
+        return patch, feat
+
+    def close(self):
+        if self.handle:
+            _lib.nbt_ig_surrogate_destroy(self.handle)
+            self.handle = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

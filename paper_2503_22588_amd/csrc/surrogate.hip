@@ -1,0 +1,382 @@
+// surrogate.hip -- learned IG surrogate: patch, conv3d trunk and MLP on BF16
+// MFMA (FP32 accumulation), top-k selection and the final pick after exact
+// rescoring.
+//
+// Matrix fragments follow v_mfma_f32_16x16x32_bf16 (gfx950): for lane l,
+// A (16 x 32) row l%16 holds k = (l/16)*8 .. +7, B (32 x 16) column l%16 holds
+// the same k, and the 16 x 16 result gives lane l column l%16, rows
+// (l/16)*4 .. +3.
+#include "internal.hpp"
+#include "ray.hpp"
+#include "surrogate.hpp"
+
+namespace nbt {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4_t mfma16(const bf16x8_t& a, const bf16x8_t& b, const f32x4_t& c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------- patch ----
+// One thread per cell: occupied and unknown voxel counts over the cell's f^3
+// voxels (voxels outside the map count as neither), divided by f^3.
+__global__ __launch_bounds__(256) void patch_kernel(DevMap m, int f, int i0x, int i0y, int i0z,
+                                                    __bf16* __restrict__ out_bf16,
+                                                    float* __restrict__ out_f32) {
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= kPatchCells) return;
+    const int cx = cell % kGrid, cy = (cell / kGrid) % kGrid, cz = cell / (kGrid * kGrid);
+    const __amdgpu_buffer_rsrc_t rs = map_rsrc(m);
+    uint32_t occ = 0, unk = 0;
+    for (int dz = 0; dz < f; ++dz) {
+        const int z = i0z + cz * f + dz;
+        if (z < 0 || z >= m.nz) continue;
+        for (int dy = 0; dy < f; ++dy) {
+            const int y = i0y + cy * f + dy;
+            if (y < 0 || y >= m.ny) continue;
+            for (int dx = 0; dx < f; ++dx) {
+                const int x = i0x + cx * f + dx;
+                if (x < 0 || x >= m.nx) continue;
+                const uint32_t w = load_word(rs, padded_offset(m, x, y, z));
+                occ += (w & kOccBit) ? 1u : 0u;
+                unk += (w == kGainOne) ? 1u : 0u;
+            }
+        }
+    }
+    const float vol = (float)(f * f * f);
+    const float fo = (float)occ / vol, fu = (float)unk / vol;
+    if (out_bf16) {
+        out_bf16[cell] = (__bf16)fo;
+        out_bf16[kPatchCells + cell] = (__bf16)fu;
+    }
+    if (out_f32) {
+        out_f32[cell] = fo;
+        out_f32[kPatchCells + cell] = fu;
+    }
+}
+
+// ---------------------------------------------------------------- conv -----
+// Implicit GEMM: out[n][m] = ReLU(bias[n] + sum_k W[n][k] A[m][k]) with m an
+// output position (z, y, x), k = ci*27 + (dz*3 + dy)*3 + dx and
+// A[m][k] = in[ci][2z+dz-1][2y+dy-1][2x+dx-1] (zero outside).  One wave per
+// 16 x 16 output tile; W is bf16 [cout][kpad], zero padded to kpad.
+__global__ __launch_bounds__(256) void conv_kernel(const __bf16* __restrict__ in, int cin, int s_in,
+                                                   const __bf16* __restrict__ w,
+                                                   const float* __restrict__ bias, int cout, int kpad,
+                                                   __bf16* __restrict__ out) {
+    const int so = s_in / 2;
+    const int M = so * so * so;
+    const int mtiles = (M + 15) / 16, ntiles = cout / 16;
+    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= mtiles * ntiles) return;
+    const int mt = tile / ntiles, nt = tile - mt * ntiles;
+    const int lane = threadIdx.x & 63;
+    const int row = lane & 15, kq = lane >> 4;
+    const int m = mt * 16 + row;
+    const int z = m / (so * so), y = (m / so) % so, x = m % so;
+    const int K = cin * 27;
+    const int n = nt * 16 + row;
+    f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < kpad; k0 += 32) {
+        bf16x8_t a, b;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = k0 + kq * 8 + e;
+            __bf16 v = (__bf16)0.0f;
+            if (k < K && m < M) {
+                const int ci = k / 27, tap = k - ci * 27;
+                const int iz = 2 * z + tap / 9 - 1, iy = 2 * y + (tap / 3) % 3 - 1, ix = 2 * x + tap % 3 - 1;
+                if (iz >= 0 && iz < s_in && iy >= 0 && iy < s_in && ix >= 0 && ix < s_in)
+                    v = in[((size_t)ci * s_in + iz) * s_in * s_in + (size_t)iy * s_in + ix];
+            }
+            a[e] = v;
+        }
+        b = *reinterpret_cast<const bf16x8_t*>(w + (size_t)n * kpad + k0 + kq * 8);
+        acc = mfma16(a, b, acc);
+    }
+    const int ncol = nt * 16 + row;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int mo = mt * 16 + kq * 4 + r;
+        if (mo < M) {
+            const float v = acc[r] + bias[ncol];
+            out[(size_t)ncol * M + mo] = (__bf16)(v > 0.0f ? v : 0.0f);
+        }
+    }
+}
+
+// c[n] = b1[n] + sum_k W1f[n][k] f[k]: the pose-independent part of fc1.
+__global__ __launch_bounds__(256) void fc1_feature_kernel(const __bf16* __restrict__ feat,
+                                                          const __bf16* __restrict__ w1f,
+                                                          const float* __restrict__ b1,
+                                                          float* __restrict__ c) {
+    const int n = threadIdx.x;
+    float s = 0.0f;
+    for (int k = 0; k < kFeat; ++k) s += (float)w1f[(size_t)n * kFeat + k] * (float)feat[k];
+    c[n] = b1[n] + s;
+}
+
+// ---------------------------------------------------------------- MLP ------
+// Per pose: h1 = ReLU(c + W1d [u, dn]) (FP32, stored BF16), h2 = ReLU(W2 h1 +
+// b2) on MFMA with W2 staged in LDS (rows padded to 264 halves so the 16
+// lanes reading one k-slice of 16 rows hit distinct banks), y = out_scale *
+// (W3 . h2 + b3).  Each wave takes 16 poses at a time.
+constexpr int kW2Stride = kHidden + 8;
+
+__global__ __launch_bounds__(256) void mlp_kernel(const float* __restrict__ poses, uint32_t n,
+                                                  float px, float py, float pz, float dist_mean,
+                                                  float dist_scale, const float* __restrict__ c,
+                                                  const float* __restrict__ w1d,
+                                                  const __bf16* __restrict__ w2,
+                                                  const float* __restrict__ b2,
+                                                  const float* __restrict__ w3, float b3,
+                                                  float out_scale, float* __restrict__ pred) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __bf16* sw2 = reinterpret_cast<__bf16*>(smem);
+    for (int i = threadIdx.x; i < kHidden * kHidden / 8; i += blockDim.x) {
+        const int r = (i * 8) / kHidden, k = (i * 8) % kHidden;
+        *reinterpret_cast<bf16x8_t*>(sw2 + r * kW2Stride + k) =
+            *reinterpret_cast<const bf16x8_t*>(w2 + (size_t)r * kHidden + k);
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int row = lane & 15, kq = lane >> 4;
+    const uint32_t ntile = (n + 15) / 16;
+    const uint32_t wave_global = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint32_t waves = gridDim.x * 4;
+    for (uint32_t t = wave_global; t < ntile; t += waves) {
+        const uint32_t p = t * 16 + row;
+        float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f, dn = 0.0f;
+        if (p < n) {
+            const float vx = poses[12 * (size_t)p + 9] - px;
+            const float vy = poses[12 * (size_t)p + 10] - py;
+            const float vz = poses[12 * (size_t)p + 11] - pz;
+            const float d = sqrtf(vx * vx + vy * vy + vz * vz);
+            const float inv = d > 0.0f ? 1.0f / d : 0.0f;
+            u0 = vx * inv;
+            u1 = vy * inv;
+            u2 = vz * inv;
+            dn = (d - dist_mean) / dist_scale;
+        }
+        bf16x8_t a[kHidden / 32];
+#pragma unroll
+        for (int ks = 0; ks < kHidden / 32; ++ks) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = ks * 32 + kq * 8 + e;
+                const float4 wd = *reinterpret_cast<const float4*>(w1d + 4 * k);
+                float h = c[k] + wd.x * u0 + wd.y * u1 + wd.z * u2 + wd.w * dn;
+                a[ks][e] = (__bf16)(h > 0.0f ? h : 0.0f);
+            }
+        }
+        float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+        for (int nt = 0; nt < kHidden / 16; ++nt) {
+            f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            const __bf16* brow = sw2 + (nt * 16 + row) * kW2Stride + kq * 8;
+#pragma unroll
+            for (int ks = 0; ks < kHidden / 32; ++ks)
+                acc = mfma16(a[ks], *reinterpret_cast<const bf16x8_t*>(brow + ks * 32), acc);
+            const int col = nt * 16 + row;
+            const float bb = b2[col], ww = w3[col];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float h2 = acc[r] + bb;
+                part[r] += ww * (h2 > 0.0f ? h2 : 0.0f);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) part[r] += __shfl_xor(part[r], o, 64);
+        }
+        if (row == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t q = t * 16 + kq * 4 + r;
+                if (q < n) pred[q] = out_scale * (part[r] + b3);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- top-k ----
+// Keys order candidates by value (descending) and index (ascending on ties):
+// (monotone bits of the value) << 32 | ~index.  NaN ranks below everything.
+__device__ __forceinline__ unsigned long long rank_key(float v, uint32_t idx) {
+    uint32_t b = __float_as_uint(v);
+    b = (v != v) ? 0u : ((b & 0x80000000u) ? ~b : (b | 0x80000000u));
+    return ((unsigned long long)b << 32) | (unsigned long long)(0xFFFFFFFFu - idx);
+}
+
+// In-LDS bitonic sort, descending, of `len` (a power of two) keys.
+__device__ void bitonic_desc(unsigned long long* s, int len) {
+    for (int size = 2; size <= len; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < len / 2; i += blockDim.x) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool desc = ((lo & size) == 0);
+                const unsigned long long a = s[lo], b = s[hi];
+                if ((a < b) == desc) {
+                    s[lo] = b;
+                    s[hi] = a;
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Stage 1: each block ranks kChunk candidates and keeps its best kKeep.
+__global__ __launch_bounds__(256) void topk_stage1_kernel(const float* __restrict__ vals, uint32_t n,
+                                                          unsigned long long* __restrict__ keep) {
+    __shared__ unsigned long long s[kChunk];
+    const uint32_t base = blockIdx.x * kChunk;
+    for (int i = threadIdx.x; i < kChunk; i += blockDim.x) {
+        const uint32_t g = base + i;
+        s[i] = g < n ? rank_key(vals[g], g) : 0ull;
+    }
+    bitonic_desc(s, kChunk);
+    for (int i = threadIdx.x; i < kKeep; i += blockDim.x) keep[(size_t)blockIdx.x * kKeep + i] = s[i];
+}
+
+// Stage 2: one block ranks all kept keys; writes the k best candidate indices.
+__global__ __launch_bounds__(1024) void topk_stage2_kernel(const unsigned long long* __restrict__ keep,
+                                                           uint32_t count, uint32_t len, uint32_t k,
+                                                           uint32_t* __restrict__ idx_out) {
+    extern __shared__ unsigned long long s2[];
+    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) s2[i] = i < count ? keep[i] : 0ull;
+    bitonic_desc(s2, (int)len);
+    for (uint32_t i = threadIdx.x; i < k; i += blockDim.x)
+        idx_out[i] = 0xFFFFFFFFu - (uint32_t)(s2[i] & 0xFFFFFFFFull);
+}
+
+__global__ void gather_poses_kernel(const float* __restrict__ poses, const uint32_t* __restrict__ idx,
+                                    uint32_t k, float* __restrict__ out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < k * 12) out[i] = poses[12 * (size_t)idx[i / 12] + i % 12];
+}
+
+// Final pick among the rescored candidates: best exact IG first, ties to the
+// lower candidate index.
+__global__ __launch_bounds__(256) void final_select_kernel(const float* __restrict__ ig_exact,
+                                                           const uint32_t* __restrict__ cand,
+                                                           uint32_t kr, uint32_t len, uint32_t k,
+                                                           uint32_t* __restrict__ idx_out,
+                                                           float* __restrict__ ig_out) {
+    __shared__ unsigned long long s[kKeep];
+    __shared__ float v[kKeep];
+    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+        s[i] = i < kr ? rank_key(ig_exact[i], cand[i]) : 0ull;
+        if (i < kr) v[i] = ig_exact[i];
+    }
+    bitonic_desc(s, (int)len);
+    for (uint32_t i = threadIdx.x; i < k; i += blockDim.x) {
+        const uint32_t c = 0xFFFFFFFFu - (uint32_t)(s[i] & 0xFFFFFFFFull);
+        idx_out[i] = c;
+        // the exact IG of candidate c: find its slot (kr <= kKeep, linear scan is tiny)
+        float val = __builtin_nanf("");
+        for (uint32_t j = 0; j < kr; ++j)
+            if (cand[j] == c) { val = v[j]; break; }
+        ig_out[i] = val;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_patch(const DevMap& m, int f, const int i0[3], __bf16* out_bf16, float* out_f32,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(patch_kernel, dim3(kPatchCells / 256), dim3(256), 0, s, m, f, i0[0], i0[1], i0[2],
+                       out_bf16, out_f32);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv(const __bf16* in, int cin, int s_in, const __bf16* w, const float* bias, int cout,
+                       int kpad, __bf16* out, hipStream_t s) {
+    const int so = s_in / 2, M = so * so * so;
+    const int tiles = ((M + 15) / 16) * (cout / 16);
+    hipLaunchKernelGGL(conv_kernel, dim3((tiles + 3) / 4), dim3(256), 0, s, in, cin, s_in, w, bias, cout,
+                       kpad, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fc1_feature(const __bf16* feat, const __bf16* w1f, const float* b1, float* c,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(fc1_feature_kernel, dim3(1), dim3(kHidden), 0, s, feat, w1f, b1, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp(const float* poses, uint32_t n, const float poi[3], float dist_mean,
+                      float dist_scale, const float* c, const float* w1d, const __bf16* w2,
+                      const float* b2, const float* w3, float b3, float out_scale, float* pred,
+                      int cu_count, hipStream_t s) {
+    static bool attr = false;
+    const size_t lds = (size_t)kHidden * kW2Stride * sizeof(__bf16);
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)mlp_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const uint32_t tiles = (n + 15) / 16;
+    uint32_t blocks = (tiles + 3) / 4;
+    const uint32_t cap = (uint32_t)cu_count;     // one block per CU holds W2 in its LDS
+    if (blocks > cap) blocks = cap;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(mlp_kernel, dim3(blocks), dim3(256), lds, s, poses, n, poi[0], poi[1], poi[2],
+                       dist_mean, dist_scale, c, w1d, w2, b2, w3, b3, out_scale, pred);
+    return hipGetLastError();
+}
+
+hipError_t launch_topk(const float* vals, uint32_t n, uint32_t k, unsigned long long* keep,
+                       uint32_t* idx_out, hipStream_t s) {
+    const uint32_t blocks = (n + kChunk - 1) / kChunk;
+    hipLaunchKernelGGL(topk_stage1_kernel, dim3(blocks), dim3(256), 0, s, vals, n, keep);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const uint32_t count = blocks * kKeep;
+    uint32_t len = 1;
+    while (len < count) len <<= 1;
+    const size_t lds = (size_t)len * sizeof(unsigned long long);
+    e = hipFuncSetAttribute((const void*)topk_stage2_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(topk_stage2_kernel, dim3(1), dim3(1024), lds, s, keep, count, len, k, idx_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_poses(const float* poses, const uint32_t* idx, uint32_t k, float* out,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(gather_poses_kernel, dim3((k * 12 + 255) / 256), dim3(256), 0, s, poses, idx, k, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_final_select(const float* ig_exact, const uint32_t* cand, uint32_t kr, uint32_t k,
+                               uint32_t* idx_out, float* ig_out, hipStream_t s) {
+    uint32_t len = 1;
+    while (len < kr) len <<= 1;
+    hipLaunchKernelGGL(final_select_kernel, dim3(1), dim3(256), 0, s, ig_exact, cand, kr, len, k, idx_out,
+                       ig_out);
+    return hipGetLastError();
+}
+
+}  // namespace nbt
+
+namespace nbt {
+
+__global__ void bf16_to_f32_kernel(const __bf16* __restrict__ in, uint32_t n, float* __restrict__ out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
+}
+
+hipError_t launch_bf16_to_f32(const __bf16* in, uint32_t n, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(bf16_to_f32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, in, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace nbt

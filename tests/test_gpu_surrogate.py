@@ -1,0 +1,145 @@
+"""GPU checks of the surrogate kernels against the float64 reference (random weights).
+
+Bar: the patch equals the reference exactly (float32 fractions); trunk
+features and predictions agree with the reference forward that rounds to
+BF16 at the same points within a BF16-derived tolerance (see the design doc:
+max |err| <= 2e-2 * max |reference|); the top-k / final pick equal an exact
+re-ranking of the GPU's own predictions and exact IG.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import surrogate as S
+from workloads import make_config, poses_shell, scene_spheres
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def nbt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2503_22588_amd as nbt
+    return nbt
+
+
+@pytest.fixture(scope="module")
+def ctx(nbt):
+    c = nbt.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _blob(seed, extent=3.2):
+    rng = np.random.default_rng(seed)
+    params = {}
+    for name, shape in S.weight_shapes():
+        fan_in = int(np.prod(shape[1:])) if len(shape) > 1 else 256
+        params[name] = rng.normal(size=shape) * (1.0 / np.sqrt(fan_in)) * (1.4 if name.endswith(".w") else 0.1)
+    return S.pack_weights(params, extent, 0.8, 0.3, 20.0)
+
+
+@pytest.fixture(scope="module")
+def setup(nbt, ctx):
+    sc = scene_spheres(n=64, voxel=0.05, n_spheres=40, seed=701)
+    poi = np.asarray(sc.poi, dtype=np.float32) + np.float32(0.07)
+    blob = _blob(702)
+    sur = nbt.Surrogate(ctx, blob)
+    m = nbt.Map(ctx, sc.P, sc.voxel, sc.origin)
+    return sc, poi, blob, sur, m
+
+
+def test_patch_exact(nbt, ctx, setup):
+    import torch
+    sc, poi, blob, sur, m = setup
+    _note("surrogate patch")
+    patch, feat = sur.features(m, poi)
+    torch.cuda.synchronize()
+    ref = S.extract_patch(sc.P, sc.voxel, sc.origin, poi, 3.2)
+    assert np.array_equal(patch.cpu().numpy(), ref.astype(np.float32))
+    # another extent and a PoI near a corner (cells partly outside the map)
+    corner = np.array([0.3, 3.0, 0.2], np.float32)
+    p2 = nbt.extract_patch(m, corner, 5.0)
+    torch.cuda.synchronize()
+    ref2 = S.extract_patch(sc.P, sc.voxel, sc.origin, corner, 5.0)
+    assert np.array_equal(p2.cpu().numpy(), ref2.astype(np.float32))
+    assert ref2[0].sum() > 0
+
+
+def test_trunk_and_predictions_close_to_reference(nbt, ctx, setup):
+    import torch
+    sc, poi, blob, sur, m = setup
+    _note("surrogate trunk + mlp")
+    params, meta = S.unpack_weights(blob)
+    _, feat = sur.features(m, poi)
+    poses = poses_shell(poi.astype(np.float64), 0.4, 1.3, 3000, seed=703)
+    pred = sur.predict(m, poi, _dev(poses))
+    torch.cuda.synchronize()
+    patch = S.extract_patch(sc.P, sc.voxel, sc.origin, poi, meta["extent"])
+    feat_ref = S.trunk(params, patch, emulate_bf16=True)
+    f = feat.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(f - feat_ref)) <= 2e-2 * max(np.max(np.abs(feat_ref)), 1e-6)
+    assert np.mean(f == feat_ref) > 0.9          # most BF16 features round identically
+    ref = S.head(params, meta, feat_ref, poses, poi, emulate_bf16=True)
+    got = pred.cpu().numpy().astype(np.float64)
+    scale = max(np.max(np.abs(ref)), 1e-6)
+    assert np.max(np.abs(got - ref)) <= 2e-2 * scale, np.max(np.abs(got - ref)) / scale
+    assert np.corrcoef(got, ref)[0, 1] > 0.999
+    # ragged counts and a tiny batch
+    for n in (1, 15, 17):
+        p = sur.predict(m, poi, _dev(poses[:n]))
+        torch.cuda.synchronize()
+        assert np.allclose(p.cpu().numpy(), got[:n], rtol=0, atol=1e-6 * scale)
+
+
+def test_select_is_exact_reranking(nbt, ctx, setup):
+    import torch
+    sc, poi, blob, sur, m = setup
+    _note("surrogate select")
+    cam = make_config(1).camera
+    poses = poses_shell(poi.astype(np.float64), 0.4, 1.3, 5000, seed=704)
+    dp = _dev(poses)
+    pred = sur.predict(m, poi, dp).cpu().numpy()
+    for kr, k in [(64, 10), (16, 16), (1, 1), (37, 5)]:
+        idx, ig = sur.select(m, cam, poi, dp, k_rescore=kr, k=k)
+        torch.cuda.synchronize()
+        cand = S.top_k(pred, kr)
+        ig_c, _ = nbt.eval_viewpoints(m, cam, _dev(poses[cand]))
+        torch.cuda.synchronize()
+        ig_c = ig_c.cpu().numpy()
+        order = sorted(range(kr), key=lambda j: (-ig_c[j], cand[j]))[:k]
+        assert list(idx.cpu().numpy()) == [int(cand[j]) for j in order], (kr, k)
+        assert np.array_equal(ig.cpu().numpy(), ig_c[order])
+    # exact IG of the picks matches the oracle
+    ref, _ = oracle.eval_viewpoints(sc, cam, poses[idx.cpu().numpy()])
+    assert np.max(np.abs(ig.cpu().numpy() - ref) / np.maximum(ref, 1e-30)) <= 1e-5
+
+
+def test_surrogate_argument_errors(nbt, ctx, setup):
+    sc, poi, blob, sur, m = setup
+    with pytest.raises(nbt.NbtError):
+        nbt.Surrogate(ctx, blob[:-8])
+    bad = bytearray(blob)
+    bad[0:4] = b"XXXX"
+    with pytest.raises(nbt.NbtError):
+        nbt.Surrogate(ctx, bytes(bad))
+    poses = _dev(poses_shell(poi.astype(np.float64), 0.4, 1.3, 20, seed=705))
+    cam = make_config(1).camera
+    with pytest.raises(nbt.NbtError):
+        sur.select(m, cam, poi, poses, k_rescore=64, k=10)       # fewer candidates than k_rescore
+    with pytest.raises(nbt.NbtError):
+        sur.select(m, cam, poi, poses, k_rescore=8, k=9)
+    with pytest.raises(nbt.NbtError):
+        sur.predict(m, (np.nan, 0, 0), poses)
