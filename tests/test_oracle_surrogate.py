@@ -113,3 +113,14 @@ def test_head_reproduces_distance_with_hand_set_weights():
 def test_top_k_tie_break():
     v = np.array([1.0, 3.0, 2.0, 3.0, 0.5, 2.0])
     assert list(S.top_k(v, 4)) == [1, 3, 2, 5]
+
+
+def test_library_blob_writer_matches_reference_layout():
+    """The package's writer and the reference's reader agree on the documented layout."""
+    from paper_2503_22588_amd.surrogate_blob import write_blob
+    rng = np.random.default_rng(9)
+    params = _random_params(rng)
+    blob = write_blob(params, 3.2, 0.85, 0.26, 41.5)
+    assert blob == S.pack_weights(params, 3.2, 0.85, 0.26, 41.5)
+    got, meta = S.unpack_weights(blob)
+    assert np.array_equal(got["fc2.w"], params["fc2.w"].astype(np.float32).astype(np.float64))
