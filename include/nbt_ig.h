@@ -306,6 +306,35 @@ int nbt_ig_surrogate_features(nbt_ig_surrogate* s, const nbt_ig_map* map, const 
  * out DEVICE float32 [2][32][32][32]. */
 int nbt_ig_extract_patch(const nbt_ig_map* map, const float poi[3], float extent, float* out, void* stream);
 
+/* ---- next-best-view selection -------------------------------------------------------
+ * The k largest of n values (DEVICE float32, e.g. the per-perspective IG of
+ * nbt_ig_eval_viewpoints: k = 1 is the NBV of an ID), best first, ties to
+ * the lower index; idx_out DEVICE uint32 [k], val_out DEVICE float32 [k] (may
+ * be NULL).  NaN ranks last.  1 <= k <= 64, k <= n <= 2^18. */
+int nbt_ig_top_k(nbt_ig_ctx* ctx, const float* values, uint32_t n, uint32_t k, uint32_t* idx_out,
+                 float* val_out, void* stream);
+
+/* ---- planner-side IG terms (Sec. IV, cost function extension) ---------------------
+ * For n_horizons candidate horizons of `steps` camera poses each (DEVICE
+ * float32 [n_horizons][steps][12]) and a buffer of n_ids information
+ * distributions (DEVICE: id_pos float32 [n_ids][n_persp][3] perspective start
+ * points, id_ig float32 [n_ids][n_persp] their g_P; index 0 = oldest):
+ *   g_out[h][k]  G(x) of Eq. 3: sum over IDs u of 1/(n_ids - u) times the
+ *                inverse-distance-weighted IG (distance power p) at the
+ *                camera centre; a centre that coincides exactly with
+ *                perspectives of an ID takes their mean IG for that ID;
+ *   o_out[h][k]  orientation factor: cos of the angle between the viewing
+ *                axis and the direction to `poi` (HOST, 3 floats), 0 when the
+ *                PoI is outside the field of view tan_half_fov_h/v;
+ *   cost_out[h]  c_I = sum_k w_i / (O G + eps) (may be NULL).
+ * FP32 distances and weights with FP64 sums; results agree with a float64
+ * evaluation to ~1e-6 relative (FoV decisions can differ within ~1e-6 of
+ * the field-of-view border). */
+int nbt_ig_eval_cost(nbt_ig_ctx* ctx, const float* id_pos, const float* id_ig, uint32_t n_ids,
+                     uint32_t n_persp, float p, const float* poses, uint32_t n_horizons, uint32_t steps,
+                     const float poi[3], float tan_half_fov_h, float tan_half_fov_v, float w_i, float eps,
+                     float* g_out, float* o_out, float* cost_out, void* stream);
+
 /* ---- helpers ------------------------------------------------------------------- */
 
 /* Endpoint grid from the paper's grid scaling (Sec. III: endpoint spacing

@@ -93,6 +93,9 @@ _sig("nbt_ig_surrogate_select", C.c_int, _vp, _vp, C.POINTER(CameraT), C.POINTER
      _u32, _vp, _vp, _vp)
 _sig("nbt_ig_surrogate_features", C.c_int, _vp, _vp, C.POINTER(C.c_float), _vp, _vp, _vp)
 _sig("nbt_ig_extract_patch", C.c_int, _vp, C.POINTER(C.c_float), C.c_float, _vp, _vp)
+_sig("nbt_ig_eval_cost", C.c_int, _vp, _vp, _vp, _u32, _u32, C.c_float, _vp, _u32, _u32, C.POINTER(C.c_float),
+     C.c_float, C.c_float, C.c_float, C.c_float, _vp, _vp, _vp, _vp)
+_sig("nbt_ig_top_k", C.c_int, _vp, _vp, _u32, _u32, _vp, _vp, _vp)
 _sig("nbt_ig_camera_from_grid", C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
      C.POINTER(CameraT))
 
@@ -457,3 +460,30 @@ class Surrogate:
             self.close()
         except Exception:
             pass
+
+
+def eval_cost(ctx: Context, id_pos, id_ig, poses, poi, tan_h, tan_v, p=2.0, w_i=1.0, eps=1e-7, stream=None):
+    """Planner terms for horizons: id_pos [NB,NP,3], id_ig [NB,NP], poses [H,K,12] (device tensors).
+    Returns (G [H,K], O [H,K], cost [H])."""
+    torch = _torch()
+    nb, np_ = int(id_ig.shape[0]), int(id_ig.shape[1])
+    h, k = int(poses.shape[0]), int(poses.shape[1])
+    G = torch.empty((h, k), dtype=torch.float32, device=poses.device)
+    O = torch.empty((h, k), dtype=torch.float32, device=poses.device)
+    cost = torch.empty(h, dtype=torch.float32, device=poses.device)
+    _check(_lib.nbt_ig_eval_cost(ctx.handle, _dev_ptr(id_pos, torch.float32, "id_pos"),
+                                 _dev_ptr(id_ig, torch.float32, "id_ig"), nb, np_, float(p),
+                                 _dev_ptr(poses, torch.float32, "poses"), h, k, _poi(poi), float(tan_h), float(tan_v),
+                                 float(w_i), float(eps), _dev_ptr(G, None, "G"), _dev_ptr(O, None, "O"),
+                                 _dev_ptr(cost, None, "cost"), _stream(stream)))
+    return G, O, cost
+
+
+def top_k(ctx: Context, values, k, stream=None):
+    """(indices int32 [k], values [k]) of the k largest values, ties to the lower index."""
+    torch = _torch()
+    idx = torch.empty(k, dtype=torch.int32, device=values.device)
+    val = torch.empty(k, dtype=torch.float32, device=values.device)
+    _check(_lib.nbt_ig_top_k(ctx.handle, _dev_ptr(values, torch.float32, "values"), values.numel(), int(k),
+                             _dev_ptr(idx, None, "idx"), _dev_ptr(val, None, "val"), _stream(stream)))
+    return idx, val

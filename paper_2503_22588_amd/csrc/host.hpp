@@ -60,6 +60,8 @@ struct nbt_ig_ctx {
     nbt::TrajMeta* meta_host = nullptr;  // pinned
     uint32_t* gbits = nullptr;
     size_t gbits_words = 0;
+    unsigned long long* topk_keep = nullptr;   // top-k selection scratch
+    size_t topk_cap = 0;
 };
 
 struct nbt_ig_map {

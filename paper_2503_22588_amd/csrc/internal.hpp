@@ -102,6 +102,11 @@ hipError_t launch_traj_union(bool global, const DevMap& m, const CamParams& c, c
 const void* batch_kernel_ptr(int waves, int depth);
 const void* batch_reset_ptr();
 
+hipError_t launch_eval_cost(const float* id_pos, const float* id_ig, uint32_t nb, uint32_t np, float p,
+                            const float* poses, uint32_t h, uint32_t k, const float poi[3], float tan_h,
+                            float tan_v, float w_i, float eps, float* g_out, float* o_out, float* cost,
+                            hipStream_t s);
+
 // Number of workgroups a perspective is split into for a launch shape.
 inline uint32_t vp_groups(const CamParams& c, const VpLaunch& L) {
     const int tw = 1 << L.tile_w_log2, th = 64 >> L.tile_w_log2;

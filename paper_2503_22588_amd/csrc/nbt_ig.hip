@@ -181,6 +181,7 @@ void nbt_ig_ctx_destroy(nbt_ig_ctx* ctx) {
     if (ctx->meta) (void)hipFree(ctx->meta);
     if (ctx->meta_host) (void)hipHostFree(ctx->meta_host);
     if (ctx->gbits) (void)hipFree(ctx->gbits);
+    if (ctx->topk_keep) (void)hipFree(ctx->topk_keep);
     delete ctx;
 }
 
@@ -460,6 +461,31 @@ int nbt_ig_ctx_get_launch(const nbt_ig_ctx* ctx, nbt_ig_launch* l) {
     l->tiles_per_wave = ctx->vp_launch.tiles_per_wave;
     l->xcd_remap = ctx->vp_launch.xcd_remap;
     l->pipeline_depth = ctx->vp_launch.depth;
+    return NBT_IG_OK;
+}
+
+int nbt_ig_eval_cost(nbt_ig_ctx* ctx, const float* id_pos, const float* id_ig, uint32_t n_ids,
+                     uint32_t n_persp, float p, const float* poses, uint32_t n_horizons, uint32_t steps,
+                     const float poi[3], float tan_half_fov_h, float tan_half_fov_v, float w_i, float eps,
+                     float* g_out, float* o_out, float* cost_out, void* stream) {
+    if (!ctx) return fail(NBT_IG_EINVAL, "ctx is NULL");
+    if (n_horizons == 0 || steps == 0) return NBT_IG_OK;
+    if (n_ids == 0 || n_persp == 0) return fail(NBT_IG_EINVAL, "the ID buffer is empty");
+    if (!id_pos || !id_ig || !poses || !poi || !g_out || !o_out)
+        return fail(NBT_IG_EINVAL, "a required pointer is NULL");
+    if (!(p >= 0.0f) || !std::isfinite(p) || !finite_pos(tan_half_fov_h) || !finite_pos(tan_half_fov_v) ||
+        !std::isfinite(w_i) || !(eps >= 0.0f) || !std::isfinite(eps))
+        return fail(NBT_IG_EINVAL, "need finite p >= 0, tangents > 0, w_i and eps >= 0");
+    if (!std::isfinite(poi[0]) || !std::isfinite(poi[1]) || !std::isfinite(poi[2]))
+        return fail(NBT_IG_EINVAL, "poi must be finite");
+    if ((uint64_t)n_horizons * steps >= (1ull << 31) || (uint64_t)n_ids * n_persp >= (1ull << 31))
+        return fail(NBT_IG_EUNSUPPORTED, "too many states or perspectives");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", ctx->device);
+    hipError_t e = launch_eval_cost(id_pos, id_ig, n_ids, n_persp, p, poses, n_horizons, steps, poi,
+                                    tan_half_fov_h, tan_half_fov_v, w_i, eps, g_out, o_out, cost_out,
+                                    (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "idw_query_kernel");
     return NBT_IG_OK;
 }
 

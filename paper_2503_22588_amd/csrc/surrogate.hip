@@ -374,6 +374,17 @@ __global__ void bf16_to_f32_kernel(const __bf16* __restrict__ in, uint32_t n, fl
     if (i < n) out[i] = (float)in[i];
 }
 
+__global__ void gather_values_kernel(const float* __restrict__ vals, const uint32_t* __restrict__ idx,
+                                     uint32_t k, float* __restrict__ out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < k) out[i] = vals[idx[i]];
+}
+
+hipError_t launch_gather_values(const float* vals, const uint32_t* idx, uint32_t k, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(gather_values_kernel, dim3((k + 255) / 256), dim3(256), 0, s, vals, idx, k, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_bf16_to_f32(const __bf16* in, uint32_t n, float* out, hipStream_t s) {
     hipLaunchKernelGGL(bf16_to_f32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, in, n, out);
     return hipGetLastError();

@@ -30,6 +30,7 @@ hipError_t launch_gather_poses(const float* poses, const uint32_t* idx, uint32_t
                                hipStream_t s);
 hipError_t launch_final_select(const float* ig_exact, const uint32_t* cand, uint32_t kr, uint32_t k,
                                uint32_t* idx_out, float* ig_out, hipStream_t s);
+hipError_t launch_gather_values(const float* vals, const uint32_t* idx, uint32_t k, float* out, hipStream_t s);
 hipError_t launch_bf16_to_f32(const __bf16* in, uint32_t n, float* out, hipStream_t s);
 
 }  // namespace nbt

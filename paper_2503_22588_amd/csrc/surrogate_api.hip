@@ -16,11 +16,6 @@ uint16_t to_bf16(float f) {                       // round to nearest, ties to e
     return (uint16_t)(u >> 16);
 }
 
-struct Blob {
-    float extent, dist_mean, dist_scale, out_scale;
-    const float* p;
-};
-
 }  // namespace
 
 struct nbt_ig_surrogate {
@@ -265,6 +260,36 @@ int nbt_ig_surrogate_features(nbt_ig_surrogate* s, const nbt_ig_map* map, const 
         hipError_t e = launch_bf16_to_f32(s->act[3], kFeat, features_out, st);
         if (e != hipSuccess) return hip_fail(e, "surrogate features");
     }
+    return NBT_IG_OK;
+}
+
+int nbt_ig_top_k(nbt_ig_ctx* ctx, const float* values, uint32_t n, uint32_t k, uint32_t* idx_out,
+                 float* val_out, void* stream) {
+    if (!ctx) return fail(NBT_IG_EINVAL, "ctx is NULL");
+    if (k < 1 || k > (uint32_t)kKeep || n < k || n > (1u << 18))
+        return fail(NBT_IG_EINVAL, "need 1 <= k <= %d and k <= n <= 2^18", kKeep);
+    if (!values || !idx_out) return fail(NBT_IG_EINVAL, "values or idx_out is NULL");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t need = (n + kChunk - 1) / kChunk * (size_t)kKeep;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (ctx->topk_cap < need) {
+            if (ctx->topk_keep) {
+                (void)hipDeviceSynchronize();
+                (void)hipFree(ctx->topk_keep);
+                ctx->topk_keep = nullptr;
+                ctx->topk_cap = 0;
+            }
+            hipError_t e = hipMalloc(&ctx->topk_keep, need * sizeof(unsigned long long));
+            if (e != hipSuccess) return hip_fail(e, "hipMalloc(top-k)");
+            ctx->topk_cap = need;
+        }
+    }
+    hipError_t e = launch_topk(values, n, k, ctx->topk_keep, idx_out, st);
+    if (e == hipSuccess && val_out) e = launch_gather_values(values, idx_out, k, val_out, st);
+    if (e != hipSuccess) return hip_fail(e, "top-k");
     return NBT_IG_OK;
 }
 

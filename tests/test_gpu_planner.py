@@ -1,0 +1,86 @@
+"""GPU checks of the planner-side terms (Eq. 3 IDW over an ID buffer, orientation factor,
+c_I) and of next-best-view selection, against the float64 references."""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import idw as I
+from oracle import surrogate as S
+from workloads import poses_ball, trajectories_walk
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nbt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2503_22588_amd as nbt
+    return nbt
+
+
+@pytest.fixture(scope="module")
+def ctx(nbt):
+    c = nbt.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.mark.parametrize("p", [2.0, 1.5])
+def test_cost_terms_match_reference(nbt, ctx, p):
+    import torch
+    print(f"[gpu] planner terms p={p}", flush=True)
+    rng = np.random.default_rng(int(p * 10))
+    poi = np.array([1.0, -0.5, 0.8])
+    nb, npp = 10, 500                                       # N_B = 10 IDs of N_P = 500 (Sec. V)
+    id_pos = np.stack([poses_ball(poi, 1.0, npp, seed=900 + u)[:, 9:12] for u in range(nb)])
+    id_ig = rng.uniform(5.0, 60.0, size=(nb, npp))
+    traj = trajectories_walk(poi, 24, 31, seed=901)          # 3 s horizon at 0.1 s: 31 states
+    # states that coincide exactly with perspectives of some IDs
+    traj[0, 0, 9:12] = id_pos[3, 7].astype(np.float32)
+    traj[1, 5, 9:12] = id_pos[9, 0].astype(np.float32)
+    id_pos = id_pos.astype(np.float32)
+    tan_h, tan_v = math.tan(math.radians(37.5)), math.tan(math.radians(32.5))
+    G, O, cost = nbt.eval_cost(ctx, _dev(id_pos), _dev(id_ig), _dev(traj), poi.astype(np.float32),
+                               tan_h, tan_v, p=p, w_i=25.0)
+    torch.cuda.synchronize()
+    G, O, cost = G.cpu().numpy(), O.cpu().numpy(), cost.cpu().numpy()
+    poi32 = poi.astype(np.float32).astype(np.float64)
+    for h in range(traj.shape[0]):
+        Gr, Or, cr = I.horizon_cost(traj[h].astype(np.float64), poi32, np.float32(tan_h), np.float32(tan_v),
+                                    id_pos.astype(np.float64), id_ig.astype(np.float32).astype(np.float64),
+                                    p=p, w_i=25.0)
+        assert np.max(np.abs(G[h] - Gr) / Gr) <= 1e-5, h
+        border = False
+        for k in range(traj.shape[1]):
+            R = traj[h, k, :9].astype(np.float64).reshape(3, 3)
+            c = R.T @ (poi32 - traj[h, k, 9:12])
+            if c[2] > 0 and (abs(abs(c[0] / c[2]) - np.float32(tan_h)) < 1e-5 or
+                             abs(abs(c[1] / c[2]) - np.float32(tan_v)) < 1e-5):
+                border = True
+                continue
+            assert abs(O[h, k] - Or[k]) <= 2e-6, (h, k)
+        if not border:
+            assert abs(cost[h] - cr) <= 1e-4 * cr, h
+
+
+def test_next_best_view_selection(nbt, ctx):
+    import torch
+    rng = np.random.default_rng(3)
+    for n, k in [(5000, 10), (65536, 64), (1024, 1), (70001, 33)]:
+        v = rng.integers(0, 50, size=n).astype(np.float32)   # many ties
+        v[rng.integers(0, n, 5)] = np.nan
+        idx, val = nbt.top_k(ctx, _dev(v), k)
+        torch.cuda.synchronize()
+        vv = np.where(np.isnan(v), -np.inf, v)
+        ref = S.top_k(vv, k)
+        assert list(idx.cpu().numpy()) == list(ref)
+        assert np.array_equal(val.cpu().numpy(), v[ref])
