@@ -46,13 +46,18 @@ def _poses(poi, n, seed):
     return poses_shell(poi.astype(np.float64), R_IN, R_OUT, n, seed)
 
 
-def build_dataset(nbt, ctx, cam, seeds, per_scene, workers=8):
-    """Patches [S,2,32,32,32] (BF16-rounded), poses [S,P,12], exact IG [S,P]."""
-    import torch
+def generate_scenes(seeds, workers=8):
+    """Scene grids on a CPU process pool; call before any GPU initialisation (the pool forks)."""
     t0 = time.time()
     with ProcessPoolExecutor(max_workers=workers) as ex:
         scenes = list(ex.map(_scene, seeds, chunksize=16))
     print(f"  {len(seeds)} scenes generated in {time.time() - t0:.1f} s", flush=True)
+    return scenes
+
+
+def build_dataset(nbt, ctx, cam, seeds, scenes, per_scene):
+    """Patches [S,2,32,32,32] (BF16-rounded), poses [S,P,12], exact IG [S,P]."""
+    import torch
     patches, poses, labels = [], [], []
     for k, (P, poi) in enumerate(scenes):
         m = nbt.Map(ctx, P, 0.05, (0.0, 0.0, 0.0))
@@ -157,15 +162,18 @@ def main():
     ap.add_argument("--eval-maps", type=int, default=16, help="held-out maps for the quality report")
     args = ap.parse_args()
 
+    seeds = [args.seed_base + i for i in range(args.scenes)]
+    print("building training set ...", flush=True)
+    scenes = generate_scenes(seeds)
+
     import torch
     import paper_2503_22588_amd as nbt
     from workloads.configs import CAM1
 
     torch.manual_seed(0)
+    torch.cuda.init()
     ctx = nbt.Context(0)
-    seeds = [args.seed_base + i for i in range(args.scenes)]
-    print("building training set ...", flush=True)
-    X, Pz, Y, pois = build_dataset(nbt, ctx, CAM1, seeds, args.per_scene)
+    X, Pz, Y, pois = build_dataset(nbt, ctx, CAM1, seeds, scenes, args.per_scene)
     poi_t = torch.from_numpy(np.stack(pois))
     out_scale = float(Y.mean())
     print(f"  {X.shape[0]} scenes x {Y.shape[1]} poses, IG mean {out_scale:.3f} std {float(Y.std()):.3f}",
