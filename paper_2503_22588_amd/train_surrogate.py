@@ -20,7 +20,6 @@ import json
 import os
 import sys
 import time
-from concurrent.futures import ProcessPoolExecutor
 
 import numpy as np
 
@@ -46,11 +45,10 @@ def _poses(poi, n, seed):
     return poses_shell(poi.astype(np.float64), R_IN, R_OUT, n, seed)
 
 
-def generate_scenes(seeds, workers=8):
-    """Scene grids on a CPU process pool; call before any GPU initialisation (the pool forks)."""
+def generate_scenes(seeds):
+    """Scene grids, generated in this process before the GPU is used."""
     t0 = time.time()
-    with ProcessPoolExecutor(max_workers=workers) as ex:
-        scenes = list(ex.map(_scene, seeds, chunksize=16))
+    scenes = [_scene(sd) for sd in seeds]
     print(f"  {len(seeds)} scenes generated in {time.time() - t0:.1f} s", flush=True)
     return scenes
 
