@@ -126,6 +126,94 @@ def extra_batch(nbt, ctx, reps):
     return res
 
 
+def extra_surrogate(nbt, ctx, n_maps=8, n_cand=65536, k_rescore=64, k=10):
+    """Surrogate-pruned selection vs plain raycasting on held-out config-1-family maps."""
+    import numpy as np
+    import torch
+    from workloads import poses_shell, scene_spheres
+    from workloads.configs import CAM1
+    path = os.path.join(ROOT, "paper_2503_22588_amd", "weights", "surrogate_cfg1.nbts")
+    if not os.path.exists(path):
+        return {"skipped": f"no trained weights at {os.path.relpath(path, ROOT)}"}
+    blob = open(path, "rb").read()
+    sur = nbt.Surrogate(ctx, blob)
+    stream = torch.cuda.current_stream()
+    agree, rel, t_plain, t_sur = [], [], [], []
+    for i in range(n_maps):
+        seed = 22588 + 5000 + 100000 + i                     # held out from training
+        sc = scene_spheres(n=64, voxel=0.05, n_spheres=10 + seed % 31, seed=seed)
+        poi = np.asarray(sc.poi, np.float32)
+        m = nbt.Map(ctx, sc.P, sc.voxel, sc.origin)
+        dp = torch.from_numpy(poses_shell(poi.astype(np.float64), 0.4, 1.3, n_cand, seed + 500)).cuda()
+        ig = torch.empty(n_cand, device="cuda")
+        t_plain.append(_timed(lambda: nbt.eval_viewpoints(m, CAM1, dp, ig_out=ig, want_steps=False), 3, stream))
+        out = {}
+
+        def sel():
+            out["r"] = sur.select(m, CAM1, poi, dp, k_rescore=k_rescore, k=k)
+
+        t_sur.append(_timed(sel, 5, stream))
+        pred = sur.predict(m, poi, dp)
+        torch.cuda.synchronize()
+        ex = ig.cpu().numpy()
+        top = set(np.lexsort((np.arange(n_cand), -ex))[:k].tolist())
+        agree.append(len(top & set(out["r"][0].cpu().numpy().tolist())) / k)
+        rel.append(float(np.mean(np.abs(pred.cpu().numpy() - ex) / np.maximum(ex, 1e-6))))
+        m.close()
+    sur.close()
+    tp, ts = float(np.mean(t_plain)), float(np.mean(t_sur))
+    return {"workload": f"{n_maps} held-out 64^3 sphere maps, {n_cand} candidates in the 0.4-1.3 m shell, "
+                        f"64x48 rays; top-{k_rescore} rescored exactly, top-{k} kept",
+            "surrogate_evals_per_s": n_cand / (ts * 1e-3), "plain_evals_per_s": n_cand / (tp * 1e-3),
+            "speedup": tp / ts, "surrogate_ms": ts, "plain_ms": tp,
+            "top10_agreement": float(np.mean(agree)), "per_map_agreement": agree,
+            "ig_mean_rel_err": float(np.mean(rel))}
+
+
+def e1_sweep(nbt, ctx, oracle_max_s=60.0):
+    """Stand-in for the paper's runtime sweep (Sec. V, online capabilities): N_P perspectives
+    sampled in the 1 m ball around the PoI (Eq. 1), endpoint grid spacing s_G * s_Vox,
+    s_Vox = 1 cm.  GPU: end-to-end (pose upload, kernels, IG download) and kernel-only;
+    CPU: the single-threaded oracle.  Prints one JSON object per configuration."""
+    import math
+    import numpy as np
+    import torch
+    import oracle
+    from workloads import poses_ball, scene_tabletop
+    sc = scene_tabletop(n=320, voxel=0.01, n_objects=120, seed=22588 + 7000)
+    poi = np.asarray(sc.extra["object_tops"][0], np.float64)
+    m = nbt.Map(ctx, sc.P, sc.voxel, sc.origin)
+    spent = 0.0
+    for s_g in (5, 50, 100, 200):
+        cam = nbt.camera_from_grid(math.radians(75.0), math.radians(65.0), 1.5, 0.01, s_g)
+        for n_p in (100, 250, 500, 750, 1000):
+            poses = poses_ball(poi, 1.0, n_p, seed=22588 + 7000 + n_p)
+            stream = torch.cuda.current_stream()
+            dp = torch.from_numpy(poses).cuda()
+            kern = _timed(lambda: nbt.eval_viewpoints(m, cam, dp, want_steps=False), 10, stream)
+
+            def end_to_end():
+                d = torch.from_numpy(poses).cuda()
+                ig, _ = nbt.eval_viewpoints(m, cam, d, want_steps=False)
+                return ig.cpu()
+
+            end_to_end()
+            t0 = time.perf_counter()
+            for _ in range(10):
+                end_to_end()
+            e2e = (time.perf_counter() - t0) * 100.0
+            row = {"s_G": s_g, "N_P": n_p, "rays_per_perspective": cam.width * cam.height,
+                   "gpu_kernel_ms": kern, "gpu_end_to_end_ms": e2e}
+            if spent < oracle_max_s:
+                t0 = time.perf_counter()
+                oracle.eval_viewpoints(sc, (cam.width, cam.height, cam.tan_half_fov_h, cam.tan_half_fov_v,
+                                            cam.range), poses)
+                dt = time.perf_counter() - t0
+                spent += dt
+                row["cpu_oracle_ms"] = dt * 1e3
+            print(json.dumps(row), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +225,8 @@ def main():
                     help="waves,tile_w_log2,tiles_per_wave,xcd_remap,pipeline_depth")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the trajectory and batched measurements")
+    ap.add_argument("--e1-sweep", action="store_true",
+                    help="only run the N_P x s_G runtime sweep at 1 cm voxels (one JSON object per line)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -163,6 +253,10 @@ def main():
 
     import paper_2503_22588_amd as nbt
     from workloads import make_config
+
+    if args.e1_sweep:
+        e1_sweep(nbt, nbt.Context(0))
+        return
 
     t_gen = time.perf_counter()
     w = make_config(2)
@@ -255,6 +349,8 @@ def main():
         result["trajectories"] = extra_trajectories(nbt, ctx, reps=3)
         _log("measuring the batched launch (config 3) ...")
         result["batched"] = extra_batch(nbt, ctx, reps=5)
+        _log("measuring the surrogate (config 5) ...")
+        result["surrogate"] = extra_surrogate(nbt, ctx)
     if not args.no_cpu_baseline:
         _log("timing the CPU oracle baseline ...")
         result["cpu_baseline"] = cpu_baseline(scene, cam, poses, args.cpu_seconds)
