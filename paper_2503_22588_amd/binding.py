@@ -20,6 +20,10 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; g.build()'` "
                       "(hipcc --offload-arch=gfx950)")
 
+# torch (device memory and streams) carries its own HIP runtime; it is loaded first
+# so that the library binds to that same runtime instead of a second copy.
+import torch as _torch_mod  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
