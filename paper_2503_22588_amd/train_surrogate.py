@@ -209,7 +209,7 @@ def main():
             loss.backward()
             opt.step()
             sched.step()
-            tot += float(loss)
+            tot += float(loss.detach())
         model.eval()
         with torch.no_grad():
             pv = model.head(model.trunk(X[va])[:, None, :].expand(-1, Y.shape[1], -1), D[va])
