@@ -126,7 +126,7 @@ def extra_batch(nbt, ctx, reps):
     return res
 
 
-def extra_surrogate(nbt, ctx, n_maps=8, n_cand=65536, k_rescore=64, k=10):
+def extra_surrogate(nbt, ctx, n_maps=8, n_cand=65536, k_rescore=256, k=10):
     """Surrogate-pruned selection vs plain raycasting on held-out config-1-family maps."""
     import numpy as np
     import torch
@@ -138,7 +138,7 @@ def extra_surrogate(nbt, ctx, n_maps=8, n_cand=65536, k_rescore=64, k=10):
     blob = open(path, "rb").read()
     sur = nbt.Surrogate(ctx, blob)
     stream = torch.cuda.current_stream()
-    agree, rel, t_plain, t_sur = [], [], [], []
+    agree, ratio, nmae, t_plain, t_sur = [], [], [], [], []
     for i in range(n_maps):
         seed = 22588 + 5000 + 100000 + i                     # held out from training
         sc = scene_spheres(n=64, voxel=0.05, n_spheres=10 + seed % 31, seed=seed)
@@ -158,7 +158,8 @@ def extra_surrogate(nbt, ctx, n_maps=8, n_cand=65536, k_rescore=64, k=10):
         ex = ig.cpu().numpy()
         top = set(np.lexsort((np.arange(n_cand), -ex))[:k].tolist())
         agree.append(len(top & set(out["r"][0].cpu().numpy().tolist())) / k)
-        rel.append(float(np.mean(np.abs(pred.cpu().numpy() - ex) / np.maximum(ex, 1e-6))))
+        ratio.append(float(out["r"][1].cpu().numpy()[0]) / float(ex.max()))
+        nmae.append(float(np.mean(np.abs(pred.cpu().numpy() - ex)) / np.mean(ex)))
         m.close()
     sur.close()
     tp, ts = float(np.mean(t_plain)), float(np.mean(t_sur))
@@ -167,7 +168,8 @@ def extra_surrogate(nbt, ctx, n_maps=8, n_cand=65536, k_rescore=64, k=10):
             "surrogate_evals_per_s": n_cand / (ts * 1e-3), "plain_evals_per_s": n_cand / (tp * 1e-3),
             "speedup": tp / ts, "surrogate_ms": ts, "plain_ms": tp,
             "top10_agreement": float(np.mean(agree)), "per_map_agreement": agree,
-            "ig_mean_rel_err": float(np.mean(rel))}
+            "best_ig_ratio": float(np.mean(ratio)), "worst_best_ig_ratio": float(np.min(ratio)),
+            "prediction_nmae": float(np.mean(nmae))}
 
 
 def e1_sweep(nbt, ctx, oracle_max_s=60.0):

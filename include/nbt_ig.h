@@ -291,7 +291,7 @@ int nbt_ig_surrogate_predict(nbt_ig_surrogate* s, const nbt_ig_map* map, const f
  * lower index), evaluate those exactly (nbt_ig_eval_viewpoints with `cam`),
  * and return the k best by exact IG: idx_out (DEVICE uint32 [k]) candidate
  * indices, ig_out (DEVICE float32 [k]) their exact IG, best first (ties to the
- * lower index).  1 <= k <= k_rescore <= 64, k_rescore <= n <= 2^18. */
+ * lower index).  1 <= k <= k_rescore <= 1024, k_rescore <= n <= 2^22. */
 int nbt_ig_surrogate_select(nbt_ig_surrogate* s, const nbt_ig_map* map, const nbt_ig_camera* cam,
                             const float poi[3], const float* poses, uint32_t n, uint32_t k_rescore,
                             uint32_t k, uint32_t* idx_out, float* ig_out, void* stream);
@@ -310,7 +310,7 @@ int nbt_ig_extract_patch(const nbt_ig_map* map, const float poi[3], float extent
  * The k largest of n values (DEVICE float32, e.g. the per-perspective IG of
  * nbt_ig_eval_viewpoints: k = 1 is the NBV of an ID), best first, ties to
  * the lower index; idx_out DEVICE uint32 [k], val_out DEVICE float32 [k] (may
- * be NULL).  NaN ranks last.  1 <= k <= 64, k <= n <= 2^18. */
+ * be NULL).  NaN ranks last.  1 <= k <= 1024, k <= n <= 2^22. */
 int nbt_ig_top_k(nbt_ig_ctx* ctx, const float* values, uint32_t n, uint32_t k, uint32_t* idx_out,
                  float* val_out, void* stream);
 

@@ -435,7 +435,7 @@ class Surrogate:
                                              n, _dev_ptr(pred, torch.float32, "pred"), _stream(stream)))
         return pred
 
-    def select(self, m: Map, cam, poi, poses, k_rescore=64, k=10, stream=None):
+    def select(self, m: Map, cam, poi, poses, k_rescore=256, k=10, stream=None):
         torch = _torch()
         idx = torch.empty(k, dtype=torch.int32, device=poses.device)
         ig = torch.empty(k, dtype=torch.float32, device=poses.device)

@@ -232,25 +232,38 @@ __device__ void bitonic_desc(unsigned long long* s, int len) {
     __syncthreads();
 }
 
-// Stage 1: each block ranks kChunk candidates and keeps its best kKeep.
-__global__ __launch_bounds__(256) void topk_stage1_kernel(const float* __restrict__ vals, uint32_t n,
-                                                          unsigned long long* __restrict__ keep) {
+// Reduction pass: each block ranks kChunk keys (from values on the first
+// pass, from kept keys afterwards) and keeps its best `keep`.
+template <bool FROM_VALUES>
+__global__ __launch_bounds__(1024) void topk_pass_kernel(const float* __restrict__ vals,
+                                                         const unsigned long long* __restrict__ keys_in,
+                                                         uint32_t n, uint32_t keep,
+                                                         unsigned long long* __restrict__ keys_out) {
     __shared__ unsigned long long s[kChunk];
     const uint32_t base = blockIdx.x * kChunk;
     for (int i = threadIdx.x; i < kChunk; i += blockDim.x) {
         const uint32_t g = base + i;
-        s[i] = g < n ? rank_key(vals[g], g) : 0ull;
+        if constexpr (FROM_VALUES)
+            s[i] = g < n ? rank_key(vals[g], g) : 0ull;
+        else
+            s[i] = g < n ? keys_in[g] : 0ull;
     }
     bitonic_desc(s, kChunk);
-    for (int i = threadIdx.x; i < kKeep; i += blockDim.x) keep[(size_t)blockIdx.x * kKeep + i] = s[i];
+    for (uint32_t i = threadIdx.x; i < keep; i += blockDim.x) keys_out[(size_t)blockIdx.x * keep + i] = s[i];
 }
 
-// Stage 2: one block ranks all kept keys; writes the k best candidate indices.
-__global__ __launch_bounds__(1024) void topk_stage2_kernel(const unsigned long long* __restrict__ keep,
-                                                           uint32_t count, uint32_t len, uint32_t k,
-                                                           uint32_t* __restrict__ idx_out) {
+// Final pass: one block ranks all remaining keys; writes the k best indices.
+__global__ __launch_bounds__(1024) void topk_final_kernel(const float* __restrict__ vals,
+                                                          const unsigned long long* __restrict__ keys,
+                                                          uint32_t count, uint32_t len, uint32_t k,
+                                                          uint32_t* __restrict__ idx_out) {
     extern __shared__ unsigned long long s2[];
-    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) s2[i] = i < count ? keep[i] : 0ull;
+    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+        if (vals)
+            s2[i] = i < count ? rank_key(vals[i], i) : 0ull;
+        else
+            s2[i] = i < count ? keys[i] : 0ull;
+    }
     bitonic_desc(s2, (int)len);
     for (uint32_t i = threadIdx.x; i < k; i += blockDim.x)
         idx_out[i] = 0xFFFFFFFFu - (uint32_t)(s2[i] & 0xFFFFFFFFull);
@@ -263,27 +276,26 @@ __global__ void gather_poses_kernel(const float* __restrict__ poses, const uint3
 }
 
 // Final pick among the rescored candidates: best exact IG first, ties to the
-// lower candidate index.
-__global__ __launch_bounds__(256) void final_select_kernel(const float* __restrict__ ig_exact,
-                                                           const uint32_t* __restrict__ cand,
-                                                           uint32_t kr, uint32_t len, uint32_t k,
-                                                           uint32_t* __restrict__ idx_out,
-                                                           float* __restrict__ ig_out) {
-    __shared__ unsigned long long s[kKeep];
-    __shared__ float v[kKeep];
+// lower candidate index.  Slot j holds candidate cand[j] with IG ig_exact[j];
+// the key carries the slot so the IG is read back without a search.
+__global__ __launch_bounds__(1024) void final_select_kernel(const float* __restrict__ ig_exact,
+                                                            const uint32_t* __restrict__ cand,
+                                                            uint32_t kr, uint32_t len, uint32_t k,
+                                                            uint32_t* __restrict__ idx_out,
+                                                            float* __restrict__ ig_out) {
+    __shared__ unsigned long long s[kMaxRescore];
     for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
-        s[i] = i < kr ? rank_key(ig_exact[i], cand[i]) : 0ull;
-        if (i < kr) v[i] = ig_exact[i];
+        // low word: candidate index (< 2^22) above the slot (< 2^10), complemented
+        s[i] = i < kr ? ((rank_key(ig_exact[i], 0u) & 0xFFFFFFFF00000000ull) |
+                         (unsigned long long)(0xFFFFFFFFu - ((cand[i] << 10) | i)))
+                      : 0ull;
     }
     bitonic_desc(s, (int)len);
     for (uint32_t i = threadIdx.x; i < k; i += blockDim.x) {
-        const uint32_t c = 0xFFFFFFFFu - (uint32_t)(s[i] & 0xFFFFFFFFull);
-        idx_out[i] = c;
-        // the exact IG of candidate c: find its slot (kr <= kKeep, linear scan is tiny)
-        float val = __builtin_nanf("");
-        for (uint32_t j = 0; j < kr; ++j)
-            if (cand[j] == c) { val = v[j]; break; }
-        ig_out[i] = val;
+        const uint32_t low = 0xFFFFFFFFu - (uint32_t)(s[i] & 0xFFFFFFFFull);
+        const uint32_t slot = low & 1023u;
+        idx_out[i] = cand[slot];
+        ig_out[i] = ig_exact[slot];
     }
 }
 
@@ -333,20 +345,46 @@ hipError_t launch_mlp(const float* poses, uint32_t n, const float poi[3], float 
     return hipGetLastError();
 }
 
-hipError_t launch_topk(const float* vals, uint32_t n, uint32_t k, unsigned long long* keep,
+static uint32_t keep_for(uint32_t k) {
+    uint32_t keep = 1;
+    while (keep < k) keep <<= 1;
+    return keep;
+}
+
+size_t topk_scratch_keys(uint32_t n, uint32_t k) {
+    const size_t first = (size_t)((n + kChunk - 1) / kChunk) * keep_for(k);
+    return 2 * first + 1;
+}
+
+hipError_t launch_topk(const float* vals, uint32_t n, uint32_t k, unsigned long long* scratch,
                        uint32_t* idx_out, hipStream_t s) {
-    const uint32_t blocks = (n + kChunk - 1) / kChunk;
-    hipLaunchKernelGGL(topk_stage1_kernel, dim3(blocks), dim3(256), 0, s, vals, n, keep);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const uint32_t count = blocks * kKeep;
+    const uint32_t keep = keep_for(k);
+    const unsigned long long* keys = nullptr;
+    uint32_t count = n;
+    const size_t half = (size_t)((n + kChunk - 1) / kChunk) * keep;
+    int flip = 0;
+    hipError_t e = hipSuccess;
+    while (count > (uint32_t)kFinalKeys) {                // reduce by kChunk / keep >= 4 per pass
+        const uint32_t blocks = (count + kChunk - 1) / kChunk;
+        unsigned long long* out = scratch + (flip ? half : 0);
+        if (!keys)
+            hipLaunchKernelGGL(topk_pass_kernel<true>, dim3(blocks), dim3(1024), 0, s, vals, nullptr, count,
+                               keep, out);
+        else
+            hipLaunchKernelGGL(topk_pass_kernel<false>, dim3(blocks), dim3(1024), 0, s, nullptr, keys, count,
+                               keep, out);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        keys = out;
+        count = blocks * keep;
+        flip ^= 1;
+    }
     uint32_t len = 1;
     while (len < count) len <<= 1;
     const size_t lds = (size_t)len * sizeof(unsigned long long);
-    e = hipFuncSetAttribute((const void*)topk_stage2_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
+    e = hipFuncSetAttribute((const void*)topk_final_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(topk_stage2_kernel, dim3(1), dim3(1024), lds, s, keep, count, len, k, idx_out);
+    hipLaunchKernelGGL(topk_final_kernel, dim3(1), dim3(1024), lds, s, keys ? nullptr : vals, keys, count, len, k,
+                       idx_out);
     return hipGetLastError();
 }
 
@@ -360,7 +398,7 @@ hipError_t launch_final_select(const float* ig_exact, const uint32_t* cand, uint
                                uint32_t* idx_out, float* ig_out, hipStream_t s) {
     uint32_t len = 1;
     while (len < kr) len <<= 1;
-    hipLaunchKernelGGL(final_select_kernel, dim3(1), dim3(256), 0, s, ig_exact, cand, kr, len, k, idx_out,
+    hipLaunchKernelGGL(final_select_kernel, dim3(1), dim3(1024), 0, s, ig_exact, cand, kr, len, k, idx_out,
                        ig_out);
     return hipGetLastError();
 }

@@ -9,8 +9,10 @@ constexpr int kGrid = 32;                          // patch cells per axis
 constexpr int kPatchCells = kGrid * kGrid * kGrid;
 constexpr int kFeat = 512;                         // trunk output: 64 channels x 2^3
 constexpr int kHidden = 256;                       // MLP width
-constexpr int kChunk = 1024;                       // candidates ranked per top-k block
-constexpr int kKeep = 64;                          // best kept per block (>= k_rescore)
+constexpr int kChunk = 4096;                       // keys ranked per top-k block
+constexpr int kMaxRescore = 1024;                  // most candidates kept by top-k / rescored exactly
+constexpr int kFinalKeys = 8192;                   // keys the single final block ranks (64 KiB LDS)
+constexpr uint32_t kMaxCandidates = 1u << 22;      // candidate index fits 22 bits (slot packing)
 constexpr int kConvIn[4] = {2, 16, 32, 64};
 constexpr int kConvOut[4] = {16, 32, 64, 64};
 
@@ -24,7 +26,9 @@ hipError_t launch_mlp(const float* poses, uint32_t n, const float poi[3], float 
                       float dist_scale, const float* c, const float* w1d, const __bf16* w2,
                       const float* b2, const float* w3, float b3, float out_scale, float* pred,
                       int cu_count, hipStream_t s);
-hipError_t launch_topk(const float* vals, uint32_t n, uint32_t k, unsigned long long* keep,
+// Keys the top-k scratch must hold for n values (two ping-pong halves).
+size_t topk_scratch_keys(uint32_t n, uint32_t k);
+hipError_t launch_topk(const float* vals, uint32_t n, uint32_t k, unsigned long long* scratch,
                        uint32_t* idx_out, hipStream_t s);
 hipError_t launch_gather_poses(const float* poses, const uint32_t* idx, uint32_t k, float* out,
                                hipStream_t s);

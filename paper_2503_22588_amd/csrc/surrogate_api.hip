@@ -168,9 +168,9 @@ int nbt_ig_surrogate_create(nbt_ig_ctx* ctx, const void* weights, size_t nbytes,
     for (int l = 0; l < 4 && e == hipSuccess; ++l, size /= 2)
         e = dalloc(s, &s->act[l], (size_t)kConvOut[l] * size * size * size);
     if (e == hipSuccess) e = dalloc(s, &s->c, kHidden);
-    if (e == hipSuccess) e = dalloc(s, &s->cand, kKeep);
-    if (e == hipSuccess) e = dalloc(s, &s->cand_poses, 12 * (size_t)kKeep);
-    if (e == hipSuccess) e = dalloc(s, &s->cand_ig, kKeep);
+    if (e == hipSuccess) e = dalloc(s, &s->cand, kMaxRescore);
+    if (e == hipSuccess) e = dalloc(s, &s->cand_poses, 12 * (size_t)kMaxRescore);
+    if (e == hipSuccess) e = dalloc(s, &s->cand_ig, kMaxRescore);
     if (e != hipSuccess) {
         nbt_ig_surrogate_destroy(s);
         return hip_fail(e, "surrogate upload");
@@ -210,17 +210,17 @@ int nbt_ig_surrogate_select(nbt_ig_surrogate* s, const nbt_ig_map* map, const nb
                             const float poi[3], const float* poses, uint32_t n, uint32_t k_rescore,
                             uint32_t k, uint32_t* idx_out, float* ig_out, void* stream) {
     if (!s) return fail(NBT_IG_EINVAL, "surrogate is NULL");
-    if (k < 1 || k > k_rescore || k_rescore > (uint32_t)kKeep)
-        return fail(NBT_IG_EINVAL, "need 1 <= k <= k_rescore <= %d", kKeep);
-    if (n < k_rescore || n > (1u << 18))
-        return fail(NBT_IG_EUNSUPPORTED, "need k_rescore <= n <= 2^18 candidates (got %u)", n);
+    if (k < 1 || k > k_rescore || k_rescore > (uint32_t)kMaxRescore)
+        return fail(NBT_IG_EINVAL, "need 1 <= k <= k_rescore <= %d", kMaxRescore);
+    if (n < k_rescore || n > kMaxCandidates)
+        return fail(NBT_IG_EUNSUPPORTED, "need k_rescore <= n <= 2^22 candidates (got %u)", n);
     if (!idx_out || !ig_out) return fail(NBT_IG_EINVAL, "idx_out or ig_out is NULL");
     CamParams cp;
     if (int rc = check_camera(cam, &cp)) return rc;
     DeviceGuard g(s->ctx->device);
     if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", s->ctx->device);
     hipStream_t st = (hipStream_t)stream;
-    const size_t blocks = (n + kChunk - 1) / kChunk;
+    const size_t need = topk_scratch_keys(n, k_rescore);
     {
         std::lock_guard<std::mutex> lk(s->ctx->mu);
         hipError_t e = hipSuccess;
@@ -229,10 +229,10 @@ int nbt_ig_surrogate_select(nbt_ig_surrogate* s, const nbt_ig_map* map, const nb
             e = hipMalloc(&s->pred, (size_t)n * sizeof(float));
             s->pred_cap = e == hipSuccess ? n : 0;
         }
-        if (e == hipSuccess && s->keep_cap < blocks * kKeep) {
+        if (e == hipSuccess && s->keep_cap < need) {
             if (s->keep) { (void)hipStreamSynchronize(st); (void)hipFree(s->keep); s->keep = nullptr; }
-            e = hipMalloc(&s->keep, blocks * kKeep * sizeof(unsigned long long));
-            s->keep_cap = e == hipSuccess ? blocks * kKeep : 0;
+            e = hipMalloc(&s->keep, need * sizeof(unsigned long long));
+            s->keep_cap = e == hipSuccess ? need : 0;
         }
         if (e != hipSuccess) return hip_fail(e, "surrogate scratch");
     }
@@ -266,13 +266,13 @@ int nbt_ig_surrogate_features(nbt_ig_surrogate* s, const nbt_ig_map* map, const 
 int nbt_ig_top_k(nbt_ig_ctx* ctx, const float* values, uint32_t n, uint32_t k, uint32_t* idx_out,
                  float* val_out, void* stream) {
     if (!ctx) return fail(NBT_IG_EINVAL, "ctx is NULL");
-    if (k < 1 || k > (uint32_t)kKeep || n < k || n > (1u << 18))
-        return fail(NBT_IG_EINVAL, "need 1 <= k <= %d and k <= n <= 2^18", kKeep);
+    if (k < 1 || k > (uint32_t)kMaxRescore || n < k || n > kMaxCandidates)
+        return fail(NBT_IG_EINVAL, "need 1 <= k <= %d and k <= n <= 2^22", kMaxRescore);
     if (!values || !idx_out) return fail(NBT_IG_EINVAL, "values or idx_out is NULL");
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", ctx->device);
     hipStream_t st = (hipStream_t)stream;
-    const size_t need = (n + kChunk - 1) / kChunk * (size_t)kKeep;
+    const size_t need = topk_scratch_keys(n, k);
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         if (ctx->topk_cap < need) {

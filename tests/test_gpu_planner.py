@@ -75,7 +75,9 @@ def test_cost_terms_match_reference(nbt, ctx, p):
 def test_next_best_view_selection(nbt, ctx):
     import torch
     rng = np.random.default_rng(3)
-    for n, k in [(5000, 10), (65536, 64), (1024, 1), (70001, 33)]:
+    # one block, one pass, and several reduction passes (k up to 1024 kept per block)
+    for n, k in [(5000, 10), (65536, 64), (1024, 1), (70001, 33), (8192, 1024), (8193, 1000),
+                 (1 << 20, 1024), (300000, 257)]:
         v = rng.integers(0, 50, size=n).astype(np.float32)   # many ties
         v[rng.integers(0, n, 5)] = np.nan
         idx, val = nbt.top_k(ctx, _dev(v), k)

@@ -112,7 +112,7 @@ def test_select_is_exact_reranking(nbt, ctx, setup):
     poses = poses_shell(poi.astype(np.float64), 0.4, 1.3, 5000, seed=704)
     dp = _dev(poses)
     pred = sur.predict(m, poi, dp).cpu().numpy()
-    for kr, k in [(64, 10), (16, 16), (1, 1), (37, 5)]:
+    for kr, k in [(64, 10), (16, 16), (1, 1), (37, 5), (1024, 64), (300, 300)]:
         idx, ig = sur.select(m, cam, poi, dp, k_rescore=kr, k=k)
         torch.cuda.synchronize()
         cand = S.top_k(pred, kr)
@@ -141,5 +141,52 @@ def test_surrogate_argument_errors(nbt, ctx, setup):
         sur.select(m, cam, poi, poses, k_rescore=64, k=10)       # fewer candidates than k_rescore
     with pytest.raises(nbt.NbtError):
         sur.select(m, cam, poi, poses, k_rescore=8, k=9)
+    many = _dev(poses_shell(poi.astype(np.float64), 0.4, 1.3, 2000, seed=706))
+    with pytest.raises(nbt.NbtError):
+        sur.select(m, cam, poi, many, k_rescore=1025, k=10)     # above the rescoring limit
     with pytest.raises(nbt.NbtError):
         sur.predict(m, (np.nan, 0, 0), poses)
+
+
+TRAINED = __import__("os").path.join(__import__("os").path.dirname(__file__), "..", "paper_2503_22588_amd",
+                                     "weights", "surrogate_cfg1.nbts")
+
+
+def test_trained_weights_parity_and_quality(nbt, ctx):
+    """The shipped weights: predictions match the float64 reference forward to the same
+    BF16 bar as random weights, and on maps held out from training the pruned selection
+    (256 of 16384 candidates rescored exactly) finds views within a few percent of the
+    exhaustive best.  Loose quality bounds: the trained network reaches NMAE ~0.04, rank
+    correlation ~0.93 and the exhaustive best on every map of a 16-map held-out set."""
+    import torch
+    blob = open(TRAINED, "rb").read()
+    params, meta = S.unpack_weights(blob)
+    sur = nbt.Surrogate(ctx, blob)
+    cam = make_config(1).camera
+    ratios, agree = [], []
+    for i in range(4):
+        seed = 22588 + 5000 + 200000 + i                    # outside the training seeds
+        sc = scene_spheres(n=64, voxel=0.05, n_spheres=10 + seed % 31, seed=seed)
+        poi = np.asarray(sc.poi, np.float32)
+        _note(f"trained surrogate, map seed {seed}")
+        m = nbt.Map(ctx, sc.P, sc.voxel, sc.origin)
+        poses = poses_shell(poi.astype(np.float64), 0.4, 1.3, 16384, seed=seed + 500)
+        dp = _dev(poses)
+        pred = sur.predict(m, poi, dp)
+        exact, _ = nbt.eval_viewpoints(m, cam, dp)
+        idx, ig = sur.select(m, cam, poi, dp, k_rescore=256, k=10)
+        torch.cuda.synchronize()
+        if i == 0:
+            patch = S.extract_patch(sc.P, sc.voxel, sc.origin, poi, meta["extent"])
+            feat_ref = S.trunk(params, patch, emulate_bf16=True)
+            ref = S.head(params, meta, feat_ref, poses[:2000], poi, emulate_bf16=True)
+            got = pred.cpu().numpy()[:2000].astype(np.float64)
+            assert np.max(np.abs(got - ref)) <= 2e-2 * np.max(np.abs(ref))
+        ex = exact.cpu().numpy().astype(np.float64)
+        top = set(np.lexsort((np.arange(ex.size), -ex))[:10].tolist())
+        agree.append(len(top & set(idx.cpu().numpy().tolist())) / 10)
+        ratios.append(float(ig.cpu().numpy()[0]) / ex.max())
+        m.close()
+    sur.close()
+    assert min(ratios) >= 0.9 and np.mean(ratios) >= 0.97, ratios
+    assert np.mean(agree) >= 0.6, agree
