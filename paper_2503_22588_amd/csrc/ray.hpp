@@ -237,19 +237,26 @@ __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buf
     }
     uint32_t n = 0;
     bool run = true;
+    // Lanes leave the loop between groups of P slots; inside a group every slot
+    // runs for every lane still in the loop, with a lane that has stopped adding
+    // nothing.  No slot is conditional, so slot u's word lives in one register
+    // across iterations and each read waits only for its own gather (the P - 1
+    // issued after it stay in flight).  A stopped lane issues at most P - 1
+    // spare gathers before it leaves.
     while (run) {
 #pragma unroll
         for (int u = 0; u < P; ++u) {
-            if (run) {
-                const uint32_t x = w[u];
-                const bool marker = x >= kMarkerMin;
-                acc += (double)__uint_as_float(marker ? 0u : (x & ~kOccBit));
-                n += marker ? 0u : 1u;
-                run = !((int)x < 0 || n >= guard);
-                dda_advance(tx, ty, tz, off, alive, t1, dxo, dyo, dzo, dtx, dty, dtz);
-                w[u] = load_word(rs, off);
-            }
+            const uint32_t x = w[u];
+            const bool take = run && x < kMarkerMin;
+            acc += (double)__uint_as_float(take ? (x & ~kOccBit) : 0u);
+            n += take ? 1u : 0u;
+            run = run && (int)x >= 0;
+            dda_advance(tx, ty, tz, off, alive, t1, dxo, dyo, dzo, dtx, dty, dtz);
+            w[u] = load_word(rs, off);
         }
+        // Every axis index moves one way only, so the border is reached within
+        // nx + ny + nz steps; the cap only guards that argument.
+        run = run && n < guard;
     }
     steps += n;
 }
@@ -310,21 +317,21 @@ __device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buff
     }
     uint32_t n = 0;
     bool run = true;
+    // Same slot structure as walk_ray_pipelined.
     while (run) {
 #pragma unroll
         for (int u = 0; u < P; ++u) {
-            if (run) {
-                const uint32_t x = w[u];
-                const bool marker = x >= kMarkerMin;
-                if (!marker && (uint32_t)bi[u] < nbits) mark((uint32_t)bi[u]);
-                n += marker ? 0u : 1u;
-                run = !((int)x < 0 || n >= guard);
-                dda_advance_idx(tx, ty, tz, off, bidx, alive, t1, dxo, dyo, dzo, dbx, dby, dbz, dtx,
-                                dty, dtz);
-                w[u] = load_word(rs, off);
-                bi[u] = bidx;
-            }
+            const uint32_t x = w[u];
+            const bool take = run && x < kMarkerMin;
+            if (take && (uint32_t)bi[u] < nbits) mark((uint32_t)bi[u]);
+            n += take ? 1u : 0u;
+            run = run && (int)x >= 0;
+            dda_advance_idx(tx, ty, tz, off, bidx, alive, t1, dxo, dyo, dzo, dbx, dby, dbz, dtx, dty,
+                            dtz);
+            w[u] = load_word(rs, off);
+            bi[u] = bidx;
         }
+        run = run && n < guard;
     }
     return n;
 }
