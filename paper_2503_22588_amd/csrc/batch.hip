@@ -32,7 +32,7 @@ void drop_graph(nbt_ig_batch* b) {
 }
 
 int set_batch_launch(nbt_ig_batch* b, const VpLaunch& L) {
-    const void* k = batch_kernel_ptr(L.waves, L.depth);
+    const void* k = batch_kernel_ptr(L.waves, L.depth, true);
     if (!k) return fail(NBT_IG_EINVAL, "unsupported batch launch shape");
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, L.waves * 64, 0);
@@ -77,7 +77,7 @@ int build_graph(nbt_ig_batch* b, const uint32_t* offsets, const float* poses, fl
     void* args[] = {&maps, &n_maps, &offsets, &cap, &cam, &poses, &groups, &tiles_x, &tiles,
                     &tw_log2, &tpw, &queue, &ig_out, &steps_out, &ws};
     hipKernelNodeParams run{};
-    run.func = const_cast<void*>(batch_kernel_ptr(L.waves, L.depth));
+    run.func = const_cast<void*>(batch_kernel_ptr(L.waves, L.depth, steps_out != nullptr));
     run.gridDim = dim3(b->grid);
     run.blockDim = dim3(L.waves * 64);
     run.sharedMemBytes = 0;

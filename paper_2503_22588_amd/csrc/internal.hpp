@@ -99,7 +99,7 @@ hipError_t launch_traj_union(bool global, const DevMap& m, const CamParams& c, c
                              uint32_t* counts, unsigned long long* visits, hipStream_t s);
 
 // Kernel entry points of the persistent batched launch (for graph nodes).
-const void* batch_kernel_ptr(int waves, int depth);
+const void* batch_kernel_ptr(int waves, int depth, bool count);
 const void* batch_reset_ptr();
 
 hipError_t launch_eval_cost(const float* id_pos, const float* id_ig, uint32_t nb, uint32_t np, float p,

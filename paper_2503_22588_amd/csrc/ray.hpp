@@ -213,9 +213,10 @@ __device__ __forceinline__ void dda_advance(float& tx, float& ty, float& tz, uin
 // flight per lane; the consumer adds gains in visiting order and stops at
 // the first Occupied word or at a sentinel (the border, or the corner word
 // the generator reads once the segment has ended).  Visits, gains and their
-// order are exactly those of walk_ray; only the reason is not reported.
-// Gathers past a stop are never consumed (and out-of-range ones read 0).
-template <int P>
+// order are exactly those of walk_ray; only the reason is not reported, and
+// the visit count only when COUNT is set.  Gathers past a stop are never
+// consumed (and out-of-range ones read 0).
+template <int P, bool COUNT>
 __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buffer_rsrc_t rs,
                                                    const RayState& r, double& acc, uint32_t& steps) {
     const int dxo = r.sx * 4;
@@ -225,7 +226,6 @@ __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buf
     const float t1 = r.t1;
     uint32_t off = padded_offset(m, r.ix, r.iy, r.iz);
     float tx = r.tx, ty = r.ty, tz = r.tz;
-    const uint32_t guard = (uint32_t)(m.nx + m.ny + m.nz + 3);
     bool alive = true;     // the generator has not yet passed the segment end
 
     uint32_t w[P];
@@ -236,6 +236,9 @@ __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buf
         w[u] = load_word(rs, off);
     }
     uint32_t n = 0;
+    // Every axis index moves one way only, so the border is reached within
+    // nx + ny + nz steps; the group budget only guards that argument.
+    uint32_t budget = (uint32_t)(m.nx + m.ny + m.nz + 3) / P + 2;
     bool run = true;
     // Lanes leave the loop between groups of P slots; inside a group every slot
     // runs for every lane still in the loop, with a lane that has stopped adding
@@ -248,17 +251,18 @@ __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buf
         for (int u = 0; u < P; ++u) {
             const uint32_t x = w[u];
             const bool take = run && x < kMarkerMin;
-            acc += (double)__uint_as_float(take ? (x & ~kOccBit) : 0u);
-            n += take ? 1u : 0u;
+            // select the word before widening it (one 32-bit select instead of two)
+            uint32_t xs = take ? x : 0u;
+            asm volatile("" : "+v"(xs));
+            acc += (double)fabsf(__uint_as_float(xs));
+            if constexpr (COUNT) n += take ? 1u : 0u;
             run = run && (int)x >= 0;
             dda_advance(tx, ty, tz, off, alive, t1, dxo, dyo, dzo, dtx, dty, dtz);
             w[u] = load_word(rs, off);
         }
-        // Every axis index moves one way only, so the border is reached within
-        // nx + ny + nz steps; the cap only guards that argument.
-        run = run && n < guard;
+        run = run && --budget != 0u;
     }
-    steps += n;
+    if constexpr (COUNT) steps += n;
 }
 
 // dda_advance plus a second index (a bitset position) that moves with the
@@ -331,7 +335,7 @@ __device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buff
             w[u] = load_word(rs, off);
             bi[u] = bidx;
         }
-        run = run && n < guard;
+        run = run && n < guard;      // the border bounds n below nx + ny + nz; guard only
     }
     return n;
 }

@@ -34,7 +34,7 @@ __device__ __forceinline__ uint32_t xcd_logical(uint32_t bid, uint32_t nb, uint3
 // tiles, then the block's sum is written (groups == 1) or combined with the
 // other slices of the perspective (last slice writes).  Called uniformly by
 // the whole block.
-template <int WAVES, int DEPTH>
+template <int WAVES, int DEPTH, bool COUNT>
 __device__ __forceinline__ void vp_group(const DevMap& m, const CamParams& c,
                                          const float* __restrict__ pp, uint32_t vp, uint32_t g,
                                          uint32_t groups, uint32_t tiles_x, uint32_t tiles,
@@ -68,7 +68,7 @@ __device__ __forceinline__ void vp_group(const DevMap& m, const CamParams& c,
                 if constexpr (DEPTH == 1)
                     walk_ray<false>(m, rs, ray, acc, steps, [](int, int, int) {});
                 else
-                    walk_ray_pipelined<DEPTH>(m, rs, ray, acc, steps);
+                    walk_ray_pipelined<DEPTH, COUNT>(m, rs, ray, acc, steps);
             } else if (st == kRayInvalid) {
                 invalid = true;
             }
@@ -122,7 +122,7 @@ __device__ __forceinline__ void vp_group(const DevMap& m, const CamParams& c,
     }
 }
 
-template <int WAVES, int DEPTH>
+template <int WAVES, int DEPTH, bool COUNT>
 __global__ __launch_bounds__(WAVES * 64) void ig_viewpoints_kernel(
     DevMap m, CamParams c, const float* __restrict__ poses, uint32_t groups, uint32_t tiles_x,
     uint32_t tiles, int tw_log2, int tpw, int remap, float* __restrict__ ig_out,
@@ -130,8 +130,8 @@ __global__ __launch_bounds__(WAVES * 64) void ig_viewpoints_kernel(
     const uint32_t bid = remap > 0 ? xcd_logical(blockIdx.x, gridDim.x, (uint32_t)remap) : blockIdx.x;
     const uint32_t vp = bid / groups;
     const uint32_t g = bid - vp * groups;
-    vp_group<WAVES, DEPTH>(m, c, poses + 12 * (size_t)vp, vp, g, groups, tiles_x, tiles, tw_log2, tpw,
-                           ig_out, steps_out, ws);
+    vp_group<WAVES, DEPTH, COUNT>(m, c, poses + 12 * (size_t)vp, vp, g, groups, tiles_x, tiles, tw_log2,
+                                  tpw, ig_out, steps_out, ws);
 }
 
 // Persistent batched launch: many maps, a CSR of perspectives per map
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(WAVES * 64) void ig_viewpoints_kernel(
 // map-major order; each workgroup pops items from an atomic counter until
 // the queue is empty, so uneven maps and perspective counts balance across
 // the chip and co-resident workgroups share one map in L2.
-template <int WAVES, int DEPTH>
+template <int WAVES, int DEPTH, bool COUNT>
 __global__ __launch_bounds__(WAVES * 64) void ig_batch_kernel(
     const DevMap* __restrict__ maps, uint32_t n_maps, const uint32_t* __restrict__ offsets,
     uint32_t capacity, CamParams c, const float* __restrict__ poses, uint32_t groups,
@@ -173,8 +173,8 @@ __global__ __launch_bounds__(WAVES * 64) void ig_batch_kernel(
         const uint32_t vp = it / groups;
         const uint32_t g = it - vp * groups;
         const DevMap m = maps[s_map];
-        vp_group<WAVES, DEPTH>(m, c, poses + 12 * (size_t)vp, vp, g, groups, tiles_x, tiles, tw_log2,
-                               tpw, ig_out, steps_out, ws);
+        vp_group<WAVES, DEPTH, COUNT>(m, c, poses + 12 * (size_t)vp, vp, g, groups, tiles_x, tiles,
+                                      tw_log2, tpw, ig_out, steps_out, ws);
     }
 }
 
@@ -270,15 +270,19 @@ hipError_t launch_eval_viewpoints(const DevMap& m, const CamParams& c, const flo
         std::apply([&](auto... a) { hipLaunchKernelGGL(kernel, grid, dim3(waves * 64), 0, s, a...); },
                    args);
     };
-#define NBT_VP_DEPTHS(W)                                          \
-    case W:                                                       \
-        switch (L.depth) {                                        \
-            case 1: go(ig_viewpoints_kernel<W, 1>, W); break;     \
-            case 2: go(ig_viewpoints_kernel<W, 2>, W); break;     \
-            case 4: go(ig_viewpoints_kernel<W, 4>, W); break;     \
-            case 8: go(ig_viewpoints_kernel<W, 8>, W); break;     \
-            default: return hipErrorInvalidValue;                 \
-        }                                                         \
+    // Without steps_out the walk skips the per-voxel visit count.
+    const bool count = steps_out != nullptr;
+#define NBT_VP_GO(W, D) \
+    (count ? go(ig_viewpoints_kernel<W, D, true>, W) : go(ig_viewpoints_kernel<W, D, false>, W))
+#define NBT_VP_DEPTHS(W)                                  \
+    case W:                                               \
+        switch (L.depth) {                                \
+            case 1: NBT_VP_GO(W, 1); break;               \
+            case 2: NBT_VP_GO(W, 2); break;               \
+            case 4: NBT_VP_GO(W, 4); break;               \
+            case 8: NBT_VP_GO(W, 8); break;               \
+            default: return hipErrorInvalidValue;         \
+        }                                                 \
         break;
     switch (L.waves) {
         NBT_VP_DEPTHS(1)
@@ -288,12 +292,15 @@ hipError_t launch_eval_viewpoints(const DevMap& m, const CamParams& c, const flo
         default:
             return hipErrorInvalidValue;
     }
+#undef NBT_VP_GO
 #undef NBT_VP_DEPTHS
     return hipGetLastError();
 }
 
-const void* batch_kernel_ptr(int waves, int depth) {
-#define NBT_BK(W, D) if (waves == W && depth == D) return (const void*)ig_batch_kernel<W, D>;
+const void* batch_kernel_ptr(int waves, int depth, bool count) {
+#define NBT_BK(W, D)                                                                      \
+    if (waves == W && depth == D)                                                         \
+        return count ? (const void*)ig_batch_kernel<W, D, true> : (const void*)ig_batch_kernel<W, D, false>;
     NBT_BK(1, 1) NBT_BK(1, 2) NBT_BK(1, 4) NBT_BK(1, 8)
     NBT_BK(2, 1) NBT_BK(2, 2) NBT_BK(2, 4) NBT_BK(2, 8)
     NBT_BK(4, 1) NBT_BK(4, 2) NBT_BK(4, 4) NBT_BK(4, 8)

@@ -121,6 +121,14 @@ def test_launch_shapes_agree(nbt, ctx, shape):
     assert np.array_equal(st.cpu().numpy().view(np.uint64), st_ref)
     rel, nan_ok = _ig_close(ig.cpu().numpy(), ig_ref)
     assert nan_ok and rel <= IG_RTOL
+    # without steps_out the kernel does not count visits; the IG is the same bits
+    ctx.set_launch(waves, twl, tpw, remap, depth)
+    try:
+        ig2, _ = nbt.eval_viewpoints(m, cam, _dev(poses), want_steps=False)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_launch()
+    assert np.array_equal(ig2.cpu().numpy().view(np.uint32), ig.cpu().numpy().view(np.uint32))
 
 
 def test_edge_cases(nbt, ctx):
