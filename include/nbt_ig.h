@@ -197,7 +197,9 @@ int nbt_ig_trace_paths(const nbt_ig_map* map, const nbt_ig_camera* cam, const fl
  * How nbt_ig_eval_viewpoints maps rays to the GPU: waves_per_group in
  * {1,2,4,8} wavefronts per workgroup; each wave walks pixel tiles of
  * (1<<tile_w_log2) x (64>>tile_w_log2) rays (tile_w_log2 in 0..6);
- * tiles_per_wave >= 1 tiles per wave per workgroup; xcd_remap = C > 0
+ * tiles_per_wave >= 1 tiles per wave per workgroup, or 0 to deal the
+ * camera's tiles evenly over as few workgroups as 16 tiles per wave allow
+ * (the default); xcd_remap = C > 0
  * deals runs of C consecutive workgroups (the workgroups of neighbouring
  * perspectives) to one XCD and its L2, 0 keeps the hardware's round-robin
  * order (C <= 65536); pipeline_depth in

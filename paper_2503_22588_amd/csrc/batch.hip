@@ -38,7 +38,7 @@ int set_batch_launch(nbt_ig_batch* b, const VpLaunch& L) {
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, L.waves * 64, 0);
     if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     if (per_cu < 1) per_cu = 1;
-    b->launch = L;
+    b->launch = resolve_launch(b->cam, L);
     b->grid = (uint32_t)(per_cu * b->ctx->cu_count);
     drop_graph(b);
     return NBT_IG_OK;
@@ -97,7 +97,7 @@ int build_graph(nbt_ig_batch* b, const uint32_t* offsets, const float* poses, fl
 bool valid_shape(const nbt_ig_launch* l) {
     const int w = l->waves_per_group, d = l->pipeline_depth == 0 ? 4 : l->pipeline_depth;
     return (w == 1 || w == 2 || w == 4 || w == 8) && l->tile_w_log2 >= 0 && l->tile_w_log2 <= 6 &&
-           l->tiles_per_wave >= 1 && l->tiles_per_wave <= 4096 && l->xcd_remap >= 0 &&
+           l->tiles_per_wave >= 0 && l->tiles_per_wave <= 4096 && l->xcd_remap >= 0 &&
            l->xcd_remap <= 65536 && (d == 1 || d == 2 || d == 4 || d == 8);
 }
 
@@ -117,7 +117,7 @@ int coordinate_search(VpLaunch start, hipStream_t s, int reps, Apply&& apply, Ru
                       VpLaunch* best_out, float* best_ms_out) {
     static const int waves[] = {2, 4, 8};
     static const int tiles[] = {2, 3, 4};
-    static const int tpws[] = {1, 4, 16};
+    static const int tpws[] = {0, 4, 16};          // 0: balanced for the camera
     static const int depths[] = {2, 4, 8};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)

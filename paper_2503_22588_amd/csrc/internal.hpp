@@ -50,7 +50,7 @@ constexpr double kFixScale = 16777216.0;     // 2^24
 struct VpLaunch {
     int waves;              // waves per workgroup (1, 2, 4, 8)
     int tile_w_log2;        // pixel tile of one wave: (1<<tile_w_log2) x (64>>tile_w_log2)
-    int tiles_per_wave;     // tiles one wave walks per workgroup
+    int tiles_per_wave;     // tiles one wave walks per workgroup; 0 = balanced for the camera
     int xcd_remap;          // 0, or runs of this many consecutive workgroups per XCD
     int depth;              // gathers in flight per lane (1, 2, 4, 8)
 };
@@ -108,11 +108,28 @@ hipError_t launch_eval_cost(const float* id_pos, const float* id_ig, uint32_t nb
                             hipStream_t s);
 
 // Number of workgroups a perspective is split into for a launch shape.
-inline uint32_t vp_groups(const CamParams& c, const VpLaunch& L) {
-    const int tw = 1 << L.tile_w_log2, th = 64 >> L.tile_w_log2;
-    const uint32_t tiles = (uint32_t)((c.W + tw - 1) / tw) * (uint32_t)((c.H + th - 1) / th);
+inline uint32_t vp_tiles(const CamParams& c, int tile_w_log2) {
+    const int tw = 1 << tile_w_log2, th = 64 >> tile_w_log2;
+    return (uint32_t)((c.W + tw - 1) / tw) * (uint32_t)((c.H + th - 1) / th);
+}
+
+// tiles_per_wave == 0: as few workgroups as 16 tiles per wave allow, with the
+// tiles dealt evenly over them (no wave of a small camera left idle, no short
+// last workgroup on a large one).
+inline VpLaunch resolve_launch(const CamParams& c, VpLaunch L) {
+    if (L.tiles_per_wave > 0) return L;
+    const uint32_t tiles = vp_tiles(c, L.tile_w_log2);
+    const uint32_t waves = (uint32_t)L.waves;
+    const uint32_t groups = (tiles + waves * 16 - 1) / (waves * 16);
+    const uint32_t tpw = (tiles + waves * groups - 1) / (waves * groups);
+    L.tiles_per_wave = (int)(tpw > 0 ? tpw : 1);
+    return L;
+}
+
+inline uint32_t vp_groups(const CamParams& c, const VpLaunch& L0) {
+    const VpLaunch L = resolve_launch(c, L0);
     const uint32_t per = (uint32_t)(L.waves * L.tiles_per_wave);
-    return (tiles + per - 1) / per;
+    return (vp_tiles(c, L.tile_w_log2) + per - 1) / per;
 }
 
 }  // namespace nbt

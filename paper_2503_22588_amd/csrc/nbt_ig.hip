@@ -442,8 +442,8 @@ int nbt_ig_ctx_set_launch(nbt_ig_ctx* ctx, const nbt_ig_launch* l) {
         return fail(NBT_IG_EINVAL, "waves_per_group must be 1, 2, 4 or 8 (got %d)", w);
     if (l->tile_w_log2 < 0 || l->tile_w_log2 > 6)
         return fail(NBT_IG_EINVAL, "tile_w_log2 must be in 0..6 (got %d)", l->tile_w_log2);
-    if (l->tiles_per_wave < 1 || l->tiles_per_wave > 4096)
-        return fail(NBT_IG_EINVAL, "tiles_per_wave must be in 1..4096 (got %d)", l->tiles_per_wave);
+    if (l->tiles_per_wave < 0 || l->tiles_per_wave > 4096)
+        return fail(NBT_IG_EINVAL, "tiles_per_wave must be in 0..4096 (got %d)", l->tiles_per_wave);
     if (l->xcd_remap < 0 || l->xcd_remap > 65536)
         return fail(NBT_IG_EINVAL, "xcd_remap must be in 0..65536 (got %d)", l->xcd_remap);
     const int d = l->pipeline_depth == 0 ? 4 : l->pipeline_depth;

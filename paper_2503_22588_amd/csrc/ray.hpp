@@ -59,6 +59,25 @@ __device__ __forceinline__ void init_axis(float O, float D, float t0, float inv,
     }
 }
 
+// Pixel of lane `lane` inside a (1 << tw_log2) x (64 >> tw_log2) tile: the
+// lane bits are dealt alternately to x and y (x first) while both sides have
+// bits left, so every aligned group of 4 lanes covers a 2 x 2 pixel block and
+// every 16 lanes a 4 x 4 block (8 x 8 tiles).  Compact lane groups gather
+// from fewer distinct cache lines than rows of 4 or 16 pixels.
+__device__ __forceinline__ void tile_pixel(int lane, int tw_log2, int& lx, int& ly) {
+    int x = 0, y = 0, bx = 0, by = 0;
+    const int th_log2 = 6 - tw_log2;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+        const int bit = (lane >> b) & 1;
+        const bool to_x = bx < tw_log2 && (by >= th_log2 || bx <= by);
+        if (to_x) x |= bit << bx++;
+        else y |= bit << by++;
+    }
+    lx = x;
+    ly = y;
+}
+
 // pose: 12 floats (row-major R camera->world, then t).
 __device__ __forceinline__ int setup_ray(const DevMap& m, const CamParams& c, const float* pose,
                                          int i, int j, RayState& r) {

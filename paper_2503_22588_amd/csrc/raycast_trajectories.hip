@@ -103,7 +103,8 @@ __global__ __launch_bounds__(kTrajWaves * 64) void traj_union_kernel(
     __syncthreads();
 
     const int wave = tid >> 6, lane = tid & 63;
-    const int lx = lane & 7, ly = lane >> 3;
+    int lx, ly;
+    tile_pixel(lane, 3, lx, ly);
     const uint32_t tiles_x = (uint32_t)(c.W + 7) / 8;
     const uint32_t tiles_pose = tiles_x * (uint32_t)((c.H + 7) / 8);
     const uint32_t total = tiles_pose * L;

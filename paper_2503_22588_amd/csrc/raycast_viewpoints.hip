@@ -49,8 +49,8 @@ __device__ __forceinline__ void vp_group(const DevMap& m, const CamParams& c,
     const int lane = threadIdx.x & 63;
     const int tw = 1 << tw_log2;
     const int th = 64 >> tw_log2;
-    const int lx = lane & (tw - 1);
-    const int ly = lane >> tw_log2;
+    int lx, ly;
+    tile_pixel(lane, tw_log2, lx, ly);
     const __amdgpu_buffer_rsrc_t rs = map_rsrc(m);
 
     double acc = 0.0;
@@ -258,7 +258,8 @@ __global__ __launch_bounds__(256) void trace_paths_kernel(DevMap m, CamParams c,
 
 hipError_t launch_eval_viewpoints(const DevMap& m, const CamParams& c, const float* poses,
                                   uint32_t n, float* ig_out, unsigned long long* steps_out,
-                                  VpAccum* ws, const VpLaunch& L, hipStream_t s) {
+                                  VpAccum* ws, const VpLaunch& L0, hipStream_t s) {
+    const VpLaunch L = resolve_launch(c, L0);
     const int tw = 1 << L.tile_w_log2, th = 64 >> L.tile_w_log2;
     const uint32_t tiles_x = (uint32_t)((c.W + tw - 1) / tw);
     const uint32_t tiles = tiles_x * (uint32_t)((c.H + th - 1) / th);

@@ -139,7 +139,7 @@ def test_batch_launch_shapes_and_autotune(nbt, ctx, uneven):
     ig = torch.empty(allp.shape[0], device="cuda")
     st = torch.empty(allp.shape[0], dtype=torch.int64, device="cuda")
     _, st_single = _single(nbt, maps, cam, poses)
-    for shape in [(1, 3, 1, 1), (8, 3, 2, 8), (2, 4, 16, 2), (4, 0, 3, 4)]:
+    for shape in [(1, 3, 1, 1), (8, 3, 2, 8), (2, 4, 16, 2), (4, 0, 3, 4), (8, 3, 0, 4)]:
         b.set_launch(*shape)
         b.run(off, dp, ig, st)
         torch.cuda.synchronize()

@@ -102,7 +102,8 @@ def test_cfg1_ig_and_steps(nbt, ctx):
 
 
 @pytest.mark.parametrize("shape", [(1, 3, 1, 0, 1), (2, 3, 2, 1, 2), (4, 4, 1, 1, 4), (8, 2, 3, 0, 8),
-                                   (4, 6, 1, 1, 1), (4, 0, 2, 1, 4), (8, 3, 8, 1, 2), (1, 3, 5, 1, 8)])
+                                   (4, 6, 1, 1, 1), (4, 0, 2, 1, 4), (8, 3, 8, 1, 2), (1, 3, 5, 1, 8),
+                                   (8, 3, 0, 0, 4), (2, 5, 0, 1, 2)])
 def test_launch_shapes_agree(nbt, ctx, shape):
     import torch
     waves, twl, tpw, remap, depth = shape
@@ -274,6 +275,8 @@ def test_argument_errors(nbt, ctx):
         assert e.value.status == nbt.binding.EINVAL
     with pytest.raises(nbt.NbtError):
         ctx.set_launch(3, 3, 1, 1)
+    with pytest.raises(nbt.NbtError):
+        ctx.set_launch(4, 3, -1, 0, 4)
     ig, _ = nbt.eval_viewpoints(m, (4, 4, 0.5, 0.5, 1.0), poses)
     torch.cuda.synchronize()
     assert np.isfinite(ig.cpu().numpy()).all()
