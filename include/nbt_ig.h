@@ -176,6 +176,12 @@ int nbt_ig_eval_trajectories(const nbt_ig_map* map, const nbt_ig_camera* cam, co
 int nbt_ig_ctx_set_lds_budget(nbt_ig_ctx* ctx, size_t bytes);
 int nbt_ig_ctx_info(const nbt_ig_ctx* ctx, int* cu_count, size_t* lds_per_group, size_t* lds_budget);
 
+/* Wavefronts per workgroup of the trajectory kernel (one workgroup per
+ * trajectory): 4, 8 or 16 (default 8); NBT_IG_EINVAL otherwise.  Results do
+ * not depend on it. */
+int nbt_ig_ctx_set_traj_waves(nbt_ig_ctx* ctx, int waves_per_group);
+int nbt_ig_ctx_get_traj_waves(const nbt_ig_ctx* ctx, int* waves_per_group);
+
 /* ---- parity mode ---------------------------------------------------------------
  * One nbt_ig_ray_digest per ray: out[p*N_E + k] for pose p, ray k.
  */

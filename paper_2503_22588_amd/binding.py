@@ -78,6 +78,8 @@ _sig("nbt_ig_eval_viewpoints", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp,
 _sig("nbt_ig_eval_trajectories", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _u32, _vp, _vp, _vp, _vp)
 _sig("nbt_ig_ctx_set_lds_budget", C.c_int, _vp, C.c_size_t)
 _sig("nbt_ig_ctx_info", C.c_int, _vp, C.POINTER(C.c_int), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t))
+_sig("nbt_ig_ctx_set_traj_waves", C.c_int, _vp, C.c_int)
+_sig("nbt_ig_ctx_get_traj_waves", C.c_int, _vp, C.POINTER(C.c_int))
 _sig("nbt_ig_trace_rays", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp)
 _sig("nbt_ig_trace_paths", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _u32, _u32, _vp, _vp, _vp)
 _sig("nbt_ig_ctx_set_launch", C.c_int, _vp, C.POINTER(LaunchT))
@@ -190,6 +192,14 @@ class Context:
 
     def set_lds_budget(self, nbytes=0):
         _check(_lib.nbt_ig_ctx_set_lds_budget(self.handle, int(nbytes)))
+
+    def set_traj_waves(self, waves_per_group=8):
+        _check(_lib.nbt_ig_ctx_set_traj_waves(self.handle, int(waves_per_group)))
+
+    def get_traj_waves(self):
+        w = C.c_int()
+        _check(_lib.nbt_ig_ctx_get_traj_waves(self.handle, C.byref(w)))
+        return w.value
 
     def info(self):
         cu, lds, budget = C.c_int(), C.c_size_t(), C.c_size_t()

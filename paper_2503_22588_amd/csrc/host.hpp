@@ -52,6 +52,7 @@ struct nbt_ig_ctx {
     nbt::VpLaunch vp_launch{8, 3, 0, 0, 4};  // 8 waves, 8x8 tiles, tiles/wave balanced per camera, no remap, 4 gathers in flight
     size_t lds_max = 0;             // device limit of LDS per workgroup (bytes)
     size_t lds_budget = 0;          // LDS a trajectory bitset may use (bytes)
+    int traj_waves = 8;             // wavefronts per trajectory workgroup (4, 8, 16)
     // trajectory workspace
     nbt::TrajBox* boxes = nullptr;
     uint32_t* over_list = nullptr;

@@ -93,10 +93,11 @@ hipError_t launch_traj_boxes(const DevMap& m, const CamParams& c, const float* p
 // Static LDS of the union kernel (its reductions); the bitset gets the rest.
 size_t traj_static_lds_bytes();
 
-hipError_t launch_traj_union(bool global, const DevMap& m, const CamParams& c, const float* poses,
-                             uint32_t L, uint32_t grid, size_t lds_bytes, const TrajBox* boxes,
-                             const uint32_t* over_list, uint32_t* gbits, float* ig_union,
-                             uint32_t* counts, unsigned long long* visits, hipStream_t s);
+hipError_t launch_traj_union(bool global, int waves, const DevMap& m, const CamParams& c,
+                             const float* poses, uint32_t L, uint32_t grid, size_t lds_bytes,
+                             const TrajBox* boxes, const uint32_t* over_list, uint32_t* gbits,
+                             float* ig_union, uint32_t* counts, unsigned long long* visits,
+                             hipStream_t s);
 
 // Kernel entry points of the persistent batched launch (for graph nodes).
 const void* batch_kernel_ptr(int waves, int depth, bool count);

@@ -371,8 +371,8 @@ int nbt_ig_eval_trajectories(const nbt_ig_map* map, const nbt_ig_camera* cam, co
     unsigned long long* vis = reinterpret_cast<unsigned long long*>(visits);
     if (meta.n_global < n_traj) {
         const size_t lds = ((size_t)meta.max_bits + 31) / 32 * 4;
-        e = launch_traj_union(false, map->dm, c, poses, poses_per_traj, n_traj, lds ? lds : 4, ctx->boxes,
-                              ctx->over_list, nullptr, ig_union, counts, vis, s);
+        e = launch_traj_union(false, ctx->traj_waves, map->dm, c, poses, poses_per_traj, n_traj,
+                              lds ? lds : 4, ctx->boxes, ctx->over_list, nullptr, ig_union, counts, vis, s);
         if (e != hipSuccess)
             return fail(e == hipErrorOutOfMemory ? NBT_IG_ENOMEM : NBT_IG_EDEVICE,
                         "traj_union_kernel(lds, %zu bytes of %zu): %s", lds, ctx->lds_max,
@@ -380,8 +380,8 @@ int nbt_ig_eval_trajectories(const nbt_ig_map* map, const nbt_ig_camera* cam, co
     }
     if (meta.n_global > 0) {
         if (int rc = ensure_global_bits(ctx, meta.global_words)) return rc;
-        e = launch_traj_union(true, map->dm, c, poses, poses_per_traj, meta.n_global, 0, ctx->boxes,
-                              ctx->over_list, ctx->gbits, ig_union, counts, vis, s);
+        e = launch_traj_union(true, ctx->traj_waves, map->dm, c, poses, poses_per_traj, meta.n_global, 0,
+                              ctx->boxes, ctx->over_list, ctx->gbits, ig_union, counts, vis, s);
         if (e != hipSuccess) return hip_fail(e, "traj_union_kernel(global)");
     }
     return NBT_IG_OK;
@@ -391,6 +391,21 @@ int nbt_ig_ctx_set_lds_budget(nbt_ig_ctx* ctx, size_t bytes) {
     if (!ctx) return fail(NBT_IG_EINVAL, "ctx is NULL");
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->lds_budget = (bytes == 0 || bytes > ctx->lds_max) ? ctx->lds_max : bytes;
+    return NBT_IG_OK;
+}
+
+int nbt_ig_ctx_set_traj_waves(nbt_ig_ctx* ctx, int waves_per_group) {
+    if (!ctx) return fail(NBT_IG_EINVAL, "ctx is NULL");
+    if (!(waves_per_group == 4 || waves_per_group == 8 || waves_per_group == 16))
+        return fail(NBT_IG_EINVAL, "trajectory waves per workgroup must be 4, 8 or 16 (got %d)", waves_per_group);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->traj_waves = waves_per_group;
+    return NBT_IG_OK;
+}
+
+int nbt_ig_ctx_get_traj_waves(const nbt_ig_ctx* ctx, int* waves_per_group) {
+    if (!ctx || !waves_per_group) return fail(NBT_IG_EINVAL, "ctx or output is NULL");
+    *waves_per_group = ctx->traj_waves;
     return NBT_IG_OK;
 }
 

@@ -21,8 +21,6 @@
 
 namespace nbt {
 
-constexpr int kTrajWaves = 16;
-
 __global__ __launch_bounds__(256) void traj_box_kernel(DevMap m, CamParams c,
                                                        const float* __restrict__ poses, uint32_t T,
                                                        uint32_t L, uint32_t budget_bits,
@@ -86,8 +84,8 @@ __global__ __launch_bounds__(256) void traj_box_kernel(DevMap m, CamParams c,
     boxes[t] = b;
 }
 
-template <bool GLOBAL>
-__global__ __launch_bounds__(kTrajWaves * 64) void traj_union_kernel(
+template <bool GLOBAL, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void traj_union_kernel(
     DevMap m, CamParams c, const float* __restrict__ poses, uint32_t L,
     const TrajBox* __restrict__ boxes, const uint32_t* __restrict__ over_list,
     uint32_t* __restrict__ gbits, float* __restrict__ ig_union, uint32_t* __restrict__ counts,
@@ -111,7 +109,7 @@ __global__ __launch_bounds__(kTrajWaves * 64) void traj_union_kernel(
     const __amdgpu_buffer_rsrc_t rs = map_rsrc(m);
     uint32_t steps = 0;
     bool invalid = false;
-    for (uint32_t tile = (uint32_t)wave; tile < total; tile += kTrajWaves) {
+    for (uint32_t tile = (uint32_t)wave; tile < total; tile += WAVES) {
         const uint32_t l = tile / tiles_pose;
         const uint32_t tt = tile - l * tiles_pose;
         const float* pp = poses + 12 * ((size_t)t * L + l);
@@ -161,10 +159,10 @@ __global__ __launch_bounds__(kTrajWaves * 64) void traj_union_kernel(
     c_unk = wave_sum_u32(c_unk);
     const unsigned long long st = wave_sum_u64((unsigned long long)steps);
     const bool wave_invalid = __ballot(invalid) != 0ull;
-    __shared__ double s_gain[kTrajWaves];
-    __shared__ unsigned long long s_steps[kTrajWaves];
-    __shared__ uint32_t s_cnt[kTrajWaves][3];
-    __shared__ int s_inv[kTrajWaves];
+    __shared__ double s_gain[WAVES];
+    __shared__ unsigned long long s_steps[WAVES];
+    __shared__ uint32_t s_cnt[WAVES][3];
+    __shared__ int s_inv[WAVES];
     if (lane == 0) {
         s_gain[wave] = gain;
         s_steps[wave] = st;
@@ -180,7 +178,7 @@ __global__ __launch_bounds__(kTrajWaves * 64) void traj_union_kernel(
     uint32_t co = 0, cf = 0, cu = 0;
     int inv = 0;
 #pragma unroll
-    for (int w = 0; w < kTrajWaves; ++w) {
+    for (int w = 0; w < WAVES; ++w) {
         g += s_gain[w];
         vs += s_steps[w];
         co += s_cnt[w][0];
@@ -197,8 +195,9 @@ __global__ __launch_bounds__(kTrajWaves * 64) void traj_union_kernel(
 }
 
 size_t traj_static_lds_bytes() {
+    // the largest static LDS among the workgroup sizes (the 16-wave kernel)
     hipFuncAttributes a;
-    if (hipFuncGetAttributes(&a, (const void*)traj_union_kernel<false>) != hipSuccess) return 4096;
+    if (hipFuncGetAttributes(&a, (const void*)traj_union_kernel<false, 16>) != hipSuccess) return 4096;
     return a.sharedSizeBytes;
 }
 
@@ -210,21 +209,34 @@ hipError_t launch_traj_boxes(const DevMap& m, const CamParams& c, const float* p
     return hipGetLastError();
 }
 
-hipError_t launch_traj_union(bool global, const DevMap& m, const CamParams& c, const float* poses,
-                             uint32_t L, uint32_t grid, size_t lds_bytes, const TrajBox* boxes,
-                             const uint32_t* over_list, uint32_t* gbits, float* ig_union,
-                             uint32_t* counts, unsigned long long* visits, hipStream_t s) {
-    if (global) {
-        hipLaunchKernelGGL(traj_union_kernel<true>, dim3(grid), dim3(kTrajWaves * 64), 0, s, m, c,
-                           poses, L, boxes, over_list, gbits, ig_union, counts, visits);
-    } else {
-        hipError_t e = hipFuncSetAttribute((const void*)traj_union_kernel<false>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+template <bool GLOBAL, int WAVES>
+static hipError_t launch_union(const DevMap& m, const CamParams& c, const float* poses, uint32_t L,
+                               uint32_t grid, size_t lds_bytes, const TrajBox* boxes,
+                               const uint32_t* over_list, uint32_t* gbits, float* ig_union,
+                               uint32_t* counts, unsigned long long* visits, hipStream_t s) {
+    const void* k = (const void*)traj_union_kernel<GLOBAL, WAVES>;
+    if (!GLOBAL) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(traj_union_kernel<false>, dim3(grid), dim3(kTrajWaves * 64), lds_bytes, s,
-                           m, c, poses, L, boxes, over_list, gbits, ig_union, counts, visits);
     }
+    hipLaunchKernelGGL((traj_union_kernel<GLOBAL, WAVES>), dim3(grid), dim3(WAVES * 64), GLOBAL ? 0 : lds_bytes,
+                       s, m, c, poses, L, boxes, over_list, gbits, ig_union, counts, visits);
     return hipGetLastError();
+}
+
+hipError_t launch_traj_union(bool global, int waves, const DevMap& m, const CamParams& c,
+                             const float* poses, uint32_t L, uint32_t grid, size_t lds_bytes,
+                             const TrajBox* boxes, const uint32_t* over_list, uint32_t* gbits,
+                             float* ig_union, uint32_t* counts, unsigned long long* visits,
+                             hipStream_t s) {
+#define NBT_TU(G, W)                                                                              \
+    if (global == G && waves == W)                                                                \
+        return launch_union<G, W>(m, c, poses, L, grid, lds_bytes, boxes, over_list, gbits, ig_union, \
+                                  counts, visits, s);
+    NBT_TU(false, 4) NBT_TU(false, 8) NBT_TU(false, 16)
+    NBT_TU(true, 4) NBT_TU(true, 8) NBT_TU(true, 16)
+#undef NBT_TU
+    return hipErrorInvalidValue;
 }
 
 }  // namespace nbt

@@ -74,7 +74,15 @@ def test_small_lds_path(nbt, ctx, small):
     sc, cam, traj, m, ref = small
     _note(f"trajectories: LDS path, context {ctx.info()}")
     ctx.set_lds_budget(0)
-    _check(_run(nbt, m, cam, traj), ref)
+    assert ctx.get_traj_waves() == 8
+    try:
+        for waves in (8, 4, 16):                  # workgroup size does not change the result
+            ctx.set_traj_waves(waves)
+            _check(_run(nbt, m, cam, traj), ref)
+    finally:
+        ctx.set_traj_waves(8)
+    with pytest.raises(nbt.NbtError):
+        ctx.set_traj_waves(6)
     assert ref[1][:, 0].min() > 1000
 
 
@@ -86,8 +94,11 @@ def test_small_global_and_mixed_paths(nbt, ctx, small):
         _check(_run(nbt, m, cam, traj), ref)
         ctx.set_lds_budget(30 * 1024)         # some fit, some do not
         _check(_run(nbt, m, cam, traj), ref)
+        ctx.set_traj_waves(4)
+        _check(_run(nbt, m, cam, traj), ref)
     finally:
         ctx.set_lds_budget(0)
+        ctx.set_traj_waves(8)
 
 
 def test_single_pose_equals_distinct_voxels(nbt, ctx, small):
