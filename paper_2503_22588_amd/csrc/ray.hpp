@@ -307,15 +307,21 @@ __device__ __forceinline__ void dda_advance_idx(float& tx, float& ty, float& tz,
     alive = go;
 }
 
-// Pipelined walk that also reports every visited voxel as a bit index into a
-// bitset over the box [lo, lo + (ax, ay, *)): ((z-lz)*ay + (y-ly))*ax + (x-lx).
-// mark(bit) runs for each visited voxel in visiting order; indices at or
-// beyond nbits (a voxel outside the box, impossible when the box contains
-// the ray's frustum) are skipped.  Returns the number of voxels visited.
-template <int P, class Mark>
+// Pipelined walk that also sets, in `bits`, the bit of every visited voxel of
+// the box [lo, lo + (ax, ay, *)): ((z-lz)*ay + (y-ly))*ax + (x-lx).  Indices
+// at or beyond nbits (a voxel outside the box, impossible when the box
+// contains the ray's frustum) are skipped.  Along a trajectory almost every
+// visit finds its bit already set, so a slot reads the word and only an unset
+// bit costs an atomic OR; the read of slot u is checked one slot later, which
+// keeps its latency off the walk.  Setting a bit twice is harmless, and a
+// stale read can only show fewer bits than are set, so the set of marked
+// voxels is exactly the set visited.  CHECK = false sets every visit with an
+// atomic OR (for bitsets in global memory, where a read could be served by a
+// stale L1 line).  Returns the number of voxels visited.
+template <int P, bool CHECK>
 __device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buffer_rsrc_t rs,
                                                   const RayState& r, int lx, int ly, int lz, int ax,
-                                                  int ay, uint32_t nbits, Mark&& mark) {
+                                                  int ay, uint32_t nbits, uint32_t* bits) {
     const int dxo = r.sx * 4;
     const int dyo = r.sy * m.px * 4;
     const int dzo = r.sz * m.px * m.py * 4;
@@ -340,13 +346,22 @@ __device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buff
     }
     uint32_t n = 0;
     bool run = true;
+    uint32_t pend_word = 0, pend_mask = 0, pend_seen = 0;    // the previous slot's mark
     // Same slot structure as walk_ray_pipelined.
     while (run) {
 #pragma unroll
         for (int u = 0; u < P; ++u) {
             const uint32_t x = w[u];
             const bool take = run && x < kMarkerMin;
-            if (take && (uint32_t)bi[u] < nbits) mark((uint32_t)bi[u]);
+            const bool mark = take && (uint32_t)bi[u] < nbits;
+            if constexpr (CHECK) {
+                if (pend_mask & ~pend_seen) atomicOr(&bits[pend_word], pend_mask);
+                pend_word = mark ? (uint32_t)bi[u] >> 5 : 0u;
+                pend_mask = mark ? 1u << ((uint32_t)bi[u] & 31u) : 0u;
+                pend_seen = bits[pend_word];
+            } else if (mark) {
+                atomicOr(&bits[(uint32_t)bi[u] >> 5], 1u << ((uint32_t)bi[u] & 31u));
+            }
             n += take ? 1u : 0u;
             run = run && (int)x >= 0;
             dda_advance_idx(tx, ty, tz, off, bidx, alive, t1, dxo, dyo, dzo, dbx, dby, dbz, dtx, dty,
@@ -356,6 +371,8 @@ __device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buff
         }
         run = run && n < guard;      // the border bounds n below nx + ny + nz; guard only
     }
+    if constexpr (CHECK)
+        if (pend_mask & ~pend_seen) atomicOr(&bits[pend_word], pend_mask);
     return n;
 }
 

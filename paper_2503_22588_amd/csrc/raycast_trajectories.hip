@@ -10,7 +10,8 @@
 //      that fit the LDS budget to the LDS kernel, the rest to global memory;
 //   2. the union kernel walks all L x N_E rays (one ray per lane, 8x8 tiles
 //      per wave, pipelined gathers) and sets one bit per visited voxel with
-//      an atomic OR (idempotent, so the set does not depend on thread order);
+//      an atomic OR (idempotent, so the set does not depend on thread order;
+//      in LDS only bits found unset take the atomic);
 //   3. the epilogue scans the bitset in a fixed order: |U|, per-state counts
 //      (exact integers) and the summed Eq. 2 gains of U (binary64).
 #include <tuple>
@@ -122,8 +123,7 @@ __global__ __launch_bounds__(WAVES * 64) void traj_union_kernel(
             RayState ray;
             const int st = setup_ray(m, c, pose, i, j, ray);
             if (st == kRayOk) {
-                steps += walk_ray_mark<4>(m, rs, ray, b.lx, b.ly, b.lz, b.ax, b.ay, b.nbits,
-                                          [&](uint32_t bit) { atomicOr(&bits[bit >> 5], 1u << (bit & 31)); });
+                steps += walk_ray_mark<4, !GLOBAL>(m, rs, ray, b.lx, b.ly, b.lz, b.ax, b.ay, b.nbits, bits);
             } else if (st == kRayInvalid) {
                 invalid = true;
             }
