@@ -32,8 +32,52 @@ BYTES_PER_STEP = 4             # one encoded map word gathered per visited voxel
 BYTES_PER_VIEWPOINT = 48 + 4 + 8   # pose in, IG and step count out
 
 
+# Sources that decide the ray kernel's binary, its launch shape and the
+# benchmark workload: counter results taken for one fingerprint are reported
+# only while it still matches.
+FINGERPRINT_FILES = (
+    "paper_2503_22588_amd/build.py",
+    "paper_2503_22588_amd/csrc/ray.hpp",
+    "paper_2503_22588_amd/csrc/raycast_viewpoints.hip",
+    "paper_2503_22588_amd/csrc/internal.hpp",
+    "paper_2503_22588_amd/csrc/host.hpp",
+    "paper_2503_22588_amd/csrc/nbt_ig.hip",
+    "paper_2503_22588_amd/csrc/map_encode.hip",
+    "workloads/configs.py",
+    "workloads/scenes.py",
+    "workloads/poses.py",
+)
+COUNTERS_PROFILE = "profiles/ig_viewpoints_cfg2_counters.md"
+
+
 def _log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_fingerprint():
+    """sha256 (first 16 hex digits) over the fingerprint files, in order."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in FINGERPRINT_FILES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read() + b"\0")
+    return h.hexdigest()[:16]
+
+
+def measured_counters():
+    """`key: value` lines of the committed counters summary, or None when it was taken
+    for other sources than the ones built now."""
+    path = os.path.join(ROOT, COUNTERS_PROFILE)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("fingerprint") != kernel_fingerprint():
+        return None
+    return vals
 
 
 def cpu_baseline(scene, cam, poses, budget_s):
@@ -229,6 +273,8 @@ def main():
                     help="skip the trajectory and batched measurements")
     ap.add_argument("--e1-sweep", action="store_true",
                     help="only run the N_P x s_G runtime sweep at 1 cm voxels (one JSON object per line)")
+    ap.add_argument("--fingerprint", action="store_true",
+                    help="print the source fingerprint the counters summary must carry and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -239,6 +285,10 @@ def main():
               "the IG evaluation shards by perspective with no exchange, and this build runs on a "
               "single MI355X.", file=sys.stderr)
         sys.exit(2)
+
+    if args.fingerprint:
+        print(kernel_fingerprint())
+        return
 
     import numpy as np
     import torch
@@ -351,8 +401,24 @@ def main():
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
             "traffic": None,
+            "algorithmic_gb_per_launch": alg_bytes / 1e9,
         },
     }
+    counters = measured_counters()
+    if counters is not None:
+        # HBM-side bytes of one launch from the committed rocprofv3 passes (FETCH_SIZE and
+        # WRITE_SIZE scaled by a copy kernel of known size), as a rate over this run's launch
+        # time so that it compares with `achieved`.
+        traffic_b = float(counters["traffic bytes per launch"])
+        result["roofline"]["traffic"] = traffic_b / (ray_ms * 1e-3) / 1e9
+        result["roofline"]["traffic_gb_per_launch"] = traffic_b / 1e9
+        result["binding_unit"] = {
+            "unit": "TA (vector-memory address path)",
+            "ta_busy_frac": float(counters["TA busy fraction"]),
+            "valu_busy_frac": float(counters["VALU busy fraction"]),
+            "tcp_accesses_per_gather": float(counters["L1 accesses per gather"]),
+            "source": COUNTERS_PROFILE,
+        }
     if not args.no_extras:
         _log("measuring trajectory IG (config 4) ...")
         result["trajectories"] = extra_trajectories(nbt, ctx, reps=3)

@@ -1,6 +1,8 @@
 // internal.hpp -- types shared by the library's translation units (not installed).
 #pragma once
 
+#include <atomic>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -109,6 +111,24 @@ hipError_t launch_eval_cost(const float* id_pos, const float* id_ig, uint32_t nb
                             hipStream_t s);
 
 // Number of workgroups a perspective is split into for a launch shape.
+// Raises a kernel's dynamic-LDS limit to `bytes` on the current device when
+// above the 64 KiB default, once per (kernel, device, size) seen; `cache`
+// is the caller's per-kernel record of the largest size set per device.
+inline hipError_t allow_dynamic_lds(const void* kernel, size_t bytes, std::atomic<size_t>* cache, int ncache) {
+    if (bytes <= 64 * 1024) return hipSuccess;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev >= 0 && dev < ncache && cache[dev].load(std::memory_order_relaxed) >= bytes) return hipSuccess;
+    e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess && dev >= 0 && dev < ncache) {
+        size_t cur = cache[dev].load(std::memory_order_relaxed);
+        while (cur < bytes && !cache[dev].compare_exchange_weak(cur, bytes)) {
+        }
+    }
+    return e;
+}
+
 inline uint32_t vp_tiles(const CamParams& c, int tile_w_log2) {
     const int tw = 1 << tile_w_log2, th = 64 >> tile_w_log2;
     return (uint32_t)((c.W + tw - 1) / tw) * (uint32_t)((c.H + th - 1) / th);
@@ -116,19 +136,28 @@ inline uint32_t vp_tiles(const CamParams& c, int tile_w_log2) {
 
 // tiles_per_wave == 0: as few workgroups as 16 tiles per wave allow, with the
 // tiles dealt evenly over them (no wave of a small camera left idle, no short
-// last workgroup on a large one).
-inline VpLaunch resolve_launch(const CamParams& c, VpLaunch L) {
+// last workgroup on a large one); when n perspectives (n > 0) would give
+// fewer than 4 workgroups per CU, each perspective is split further (down to
+// one tile per wave) so that small calls still fill the chip.
+inline VpLaunch resolve_launch(const CamParams& c, VpLaunch L, uint32_t n = 0, int cu_count = 0) {
     if (L.tiles_per_wave > 0) return L;
     const uint32_t tiles = vp_tiles(c, L.tile_w_log2);
     const uint32_t waves = (uint32_t)L.waves;
-    const uint32_t groups = (tiles + waves * 16 - 1) / (waves * 16);
+    uint32_t groups = (tiles + waves * 16 - 1) / (waves * 16);
+    const uint64_t want = 4ull * (uint64_t)(cu_count > 0 ? cu_count : 0);
+    if (n > 0 && (uint64_t)n * groups < want) {
+        const uint32_t most = (tiles + waves - 1) / waves;
+        const uint64_t g = (want + n - 1) / n;
+        groups = (uint32_t)(g < most ? g : most);
+        if (groups < 1) groups = 1;
+    }
     const uint32_t tpw = (tiles + waves * groups - 1) / (waves * groups);
     L.tiles_per_wave = (int)(tpw > 0 ? tpw : 1);
     return L;
 }
 
-inline uint32_t vp_groups(const CamParams& c, const VpLaunch& L0) {
-    const VpLaunch L = resolve_launch(c, L0);
+inline uint32_t vp_groups(const CamParams& c, const VpLaunch& L0, uint32_t n = 0, int cu_count = 0) {
+    const VpLaunch L = resolve_launch(c, L0, n, cu_count);
     const uint32_t per = (uint32_t)(L.waves * L.tiles_per_wave);
     return (vp_tiles(c, L.tile_w_log2) + per - 1) / per;
 }

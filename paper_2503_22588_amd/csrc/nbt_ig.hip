@@ -326,7 +326,7 @@ int nbt_ig_eval_viewpoints(const nbt_ig_map* map, const nbt_ig_camera* cam, cons
     if (n == 0) return NBT_IG_OK;
     if (!poses || !ig_out) return fail(NBT_IG_EINVAL, "poses or ig_out is NULL");
     nbt_ig_ctx* ctx = map->ctx;
-    const VpLaunch L = ctx->vp_launch;
+    const VpLaunch L = resolve_launch(c, ctx->vp_launch, n, ctx->cu_count);
     const uint64_t groups = vp_groups(c, L);
     if ((uint64_t)n * groups >= (1ull << 32))
         return fail(NBT_IG_EUNSUPPORTED, "%u perspectives x %llu workgroups exceed the grid limit", n,

@@ -216,7 +216,8 @@ static hipError_t launch_union(const DevMap& m, const CamParams& c, const float*
                                uint32_t* counts, unsigned long long* visits, hipStream_t s) {
     const void* k = (const void*)traj_union_kernel<GLOBAL, WAVES>;
     if (!GLOBAL) {
-        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        static std::atomic<size_t> lds_set[64];
+        const hipError_t e = allow_dynamic_lds(k, lds_bytes, lds_set, 64);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((traj_union_kernel<GLOBAL, WAVES>), dim3(grid), dim3(WAVES * 64), GLOBAL ? 0 : lds_bytes,

@@ -9,9 +9,7 @@ constexpr int kGrid = 32;                          // patch cells per axis
 constexpr int kPatchCells = kGrid * kGrid * kGrid;
 constexpr int kFeat = 512;                         // trunk output: 64 channels x 2^3
 constexpr int kHidden = 256;                       // MLP width
-constexpr int kChunk = 4096;                       // keys ranked per top-k block
 constexpr int kMaxRescore = 1024;                  // most candidates kept by top-k / rescored exactly
-constexpr int kFinalKeys = 8192;                   // keys the single final block ranks (64 KiB LDS)
 constexpr uint32_t kMaxCandidates = 1u << 22;      // candidate index fits 22 bits (slot packing)
 constexpr int kConvIn[4] = {2, 16, 32, 64};
 constexpr int kConvOut[4] = {16, 32, 64, 64};
