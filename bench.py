@@ -269,6 +269,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default=None,
                     help="waves,tile_w_log2,tiles_per_wave,xcd_remap,pipeline_depth")
+    ap.add_argument("--layout", choices=("linear", "brick4"), default=None,
+                    help="map storage order (default: the library's)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the trajectory and batched measurements")
     ap.add_argument("--e1-sweep", action="store_true",
@@ -319,6 +321,8 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     ctx = nbt.Context(0)
+    if args.layout:
+        ctx.set_map_layout({"linear": nbt.binding.LAYOUT_LINEAR, "brick4": nbt.binding.LAYOUT_BRICK4}[args.layout])
     if args.launch:
         ctx.set_launch(*[int(v) for v in args.launch.split(",")])
     prob = torch.from_numpy(scene.P).cuda()
@@ -388,6 +392,7 @@ def main():
             "rays_per_perspective": cam.width * cam.height,
             "map": list(scene.P.shape[::-1]),
             "launch": ctx.get_launch(),
+            "map_layout": ["linear", "brick4"][m.info()["layout"]],
         },
         "rays_per_s": rays * args.steps / wall,
         "voxel_steps_per_s": total_steps * args.steps / wall,

@@ -76,6 +76,12 @@ enum {
 /* Voxel states (Eq. 2). */
 enum { NBT_IG_OCCUPIED = 1, NBT_IG_FREE = 2, NBT_IG_UNKNOWN = 3 };
 
+/* Device storage order of an encoded map (nbt_ig_ctx_set_map_layout). */
+enum {
+    NBT_IG_LAYOUT_LINEAR = 0,   /* x fastest over the bordered grid */
+    NBT_IG_LAYOUT_BRICK4 = 1    /* 4x4x4 bricks of 256 B (x fastest inside), bricks x fastest */
+};
+
 typedef struct nbt_ig_ctx nbt_ig_ctx;
 typedef struct nbt_ig_map nbt_ig_map;
 typedef struct nbt_ig_batch nbt_ig_batch;
@@ -112,12 +118,21 @@ typedef struct {
 int nbt_ig_ctx_create(int device, nbt_ig_ctx** out);
 void nbt_ig_ctx_destroy(nbt_ig_ctx* ctx);       /* NULL is a no-op; caller syncs its streams first */
 
+/* Storage order of the maps this context creates from now on
+ * (NBT_IG_LAYOUT_*; NBT_IG_EINVAL otherwise).  Every call gives the same
+ * results on either; the order only changes how many cache lines one
+ * 64-ray gather touches.  The getter reports the current setting;
+ * nbt_ig_map_layout the order of an existing map. */
+int nbt_ig_ctx_set_map_layout(nbt_ig_ctx* ctx, int layout);
+int nbt_ig_ctx_get_map_layout(const nbt_ig_ctx* ctx, int* layout);
+
 /* ---- maps -------------------------------------------------------------------
  * Copies the occupancy grid `prob` (float32 [nz][ny][nx], x fastest, values
  * in [0,1]; HOST or DEVICE pointer) into a device-resident encoded map: each
  * voxel stores its Eq. 2 gain with the sign bit marking Occupied, inside a
- * one-voxel border that stops every ray leaving the map.  1 <= n <= 4096 per
- * axis and (nx+2)(ny+2)(nz+2) < 2^30.  `origin` (HOST, 3 floats) is the world
+ * one-voxel border that stops every ray leaving the map, stored in the
+ * context's map layout.  1 <= n <= 4096 per axis and (nx+2)(ny+2)(nz+2) <
+ * 2^30 (for 4x4x4 bricks: the brick-padded count < 2^30).  `origin` (HOST, 3 floats) is the world
  * position of the min corner of voxel (0,0,0); `voxel_size` > 0 is s_Vox.
  * `cls` may be NULL (0.5/0.5); 0 <= free_threshold <= occ_threshold <= 1.
  * Probabilities outside [0,1] or NaN give NBT_IG_EINVAL (checked on the
@@ -142,6 +157,7 @@ int nbt_ig_map_check(nbt_ig_map* map, void* stream);
 /* Dimensions of a map (HOST outputs, any may be NULL). */
 int nbt_ig_map_info(const nbt_ig_map* map, int* nx, int* ny, int* nz, float* voxel_size,
                     float origin[3], size_t* device_bytes);
+int nbt_ig_map_layout(const nbt_ig_map* map, int* layout);
 
 /* ---- per-perspective IG (Sec. III, IG calculation) ----------------------------
  * ig_out[p] = g_P of pose p: the mean over its N_E rays of the ray gain g_R

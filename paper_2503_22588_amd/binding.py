@@ -28,6 +28,7 @@ _lib = C.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
 RAY_MISS, RAY_HIT, RAY_END, RAY_EXIT, RAY_INVALID = 0, 1, 2, 3, 4
+LAYOUT_LINEAR, LAYOUT_BRICK4 = 0, 1
 OCCUPIED, FREE, UNKNOWN = 1, 2, 3
 
 
@@ -79,6 +80,9 @@ _sig("nbt_ig_eval_trajectories", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _u
 _sig("nbt_ig_ctx_set_lds_budget", C.c_int, _vp, C.c_size_t)
 _sig("nbt_ig_ctx_info", C.c_int, _vp, C.POINTER(C.c_int), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t))
 _sig("nbt_ig_ctx_set_traj_waves", C.c_int, _vp, C.c_int)
+_sig("nbt_ig_ctx_set_map_layout", C.c_int, _vp, C.c_int)
+_sig("nbt_ig_ctx_get_map_layout", C.c_int, _vp, C.POINTER(C.c_int))
+_sig("nbt_ig_map_layout", C.c_int, _vp, C.POINTER(C.c_int))
 _sig("nbt_ig_ctx_get_traj_waves", C.c_int, _vp, C.POINTER(C.c_int))
 _sig("nbt_ig_trace_rays", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp)
 _sig("nbt_ig_trace_paths", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _u32, _u32, _vp, _vp, _vp)
@@ -193,6 +197,15 @@ class Context:
     def set_lds_budget(self, nbytes=0):
         _check(_lib.nbt_ig_ctx_set_lds_budget(self.handle, int(nbytes)))
 
+    def set_map_layout(self, layout):
+        """Storage order of maps created from now on: LAYOUT_LINEAR or LAYOUT_BRICK4."""
+        _check(_lib.nbt_ig_ctx_set_map_layout(self.handle, int(layout)))
+
+    def get_map_layout(self):
+        v = C.c_int()
+        _check(_lib.nbt_ig_ctx_get_map_layout(self.handle, C.byref(v)))
+        return v.value
+
     def set_traj_waves(self, waves_per_group=8):
         _check(_lib.nbt_ig_ctx_set_traj_waves(self.handle, int(waves_per_group)))
 
@@ -260,8 +273,10 @@ class Map:
         nb = C.c_size_t()
         _check(_lib.nbt_ig_map_info(self.handle, C.byref(nx), C.byref(ny), C.byref(nz), C.byref(vs),
                                     org, C.byref(nb)))
+        lay = C.c_int()
+        _check(_lib.nbt_ig_map_layout(self.handle, C.byref(lay)))
         return {"dims": (nx.value, ny.value, nz.value), "voxel": vs.value, "origin": tuple(org),
-                "device_bytes": nb.value}
+                "device_bytes": nb.value, "layout": lay.value}
 
     def close(self):
         if self.handle:

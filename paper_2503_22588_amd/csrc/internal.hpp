@@ -19,15 +19,36 @@ constexpr uint32_t kSentinel = 0xFFFFFFFFu;
 constexpr uint32_t kOccBit = 0x80000000u;
 constexpr uint32_t kGainOne = 0x3F800000u;   // 1.0f: the gain of an Unknown voxel
 
+// Storage order of the encoded words over the padded grid (X, Y, Z) =
+// (x+1, y+1, z+1):
+//   kLayoutLinear  x fastest: (Z*py + Y)*px + X;
+//   kLayoutBrick4  4x4x4 bricks of 64 words (256 B = two 128-B lines), x fastest
+//                  inside a brick and bricks x fastest over the brick grid:
+//                  ((Z/4*nby + Y/4)*nbx + X/4)*64 + (Z%4)*16 + (Y%4)*4 + X%4.
+// Padding up to whole bricks holds the sentinel as well.
+constexpr int kLayoutLinear = NBT_IG_LAYOUT_LINEAR;
+constexpr int kLayoutBrick4 = NBT_IG_LAYOUT_BRICK4;
+
 // Device view of an encoded map (passed to kernels by value).
 struct DevMap {
-    const uint32_t* enc;    // padded grid, x fastest: ((z+1)*py + (y+1))*px + (x+1)
+    const uint32_t* enc;    // encoded words in `layout` order
     uint32_t bytes;         // size of enc in bytes (< 2^32)
     int nx, ny, nz;         // real dimensions
     int px, py, pz;         // padded dimensions (n + 2)
+    int layout;             // kLayoutLinear or kLayoutBrick4
+    int nbx, nby, nbz;      // bricks per axis over the padded grid (kLayoutBrick4)
     float inv_s;            // 1/voxel_size (binary32)
     float ox, oy, oz;       // origin
 };
+
+// Byte offset of voxel (x, y, z), real coordinates in [-1, n] (the border
+// included), in either layout.
+__host__ __device__ inline uint32_t voxel_offset(const DevMap& m, int x, int y, int z) {
+    const uint32_t X = (uint32_t)(x + 1), Y = (uint32_t)(y + 1), Z = (uint32_t)(z + 1);
+    if (m.layout == kLayoutLinear) return ((Z * (uint32_t)m.py + Y) * (uint32_t)m.px + X) * 4u;
+    const uint32_t brick = ((Z >> 2) * (uint32_t)m.nby + (Y >> 2)) * (uint32_t)m.nbx + (X >> 2);
+    return (brick * 64u + ((Z & 3u) << 4 | (Y & 3u) << 2 | (X & 3u))) * 4u;
+}
 
 // Endpoint-grid parameters derived once per launch on the host.
 struct CamParams {

@@ -3,50 +3,62 @@
 // Each voxel is classified once (Occupied if P > occ, Free if P < free,
 // Unknown otherwise) and stored as its Eq. 2 gain (1-P, P or 1) in float32
 // bits, with the sign bit set for Occupied.  A one-voxel border of sentinel
-// words surrounds the map.  The walk then needs one 4-byte gather and one
-// signed compare per voxel: no probability, no threshold and no bounds
-// test is evaluated per step.  Streaming kernel, about 8 B per voxel.
+// words surrounds the map (and fills the padding of the brick layout).  The
+// walk then needs one 4-byte gather and one signed compare per voxel: no
+// probability, no threshold and no bounds test is evaluated per step.
+// Streaming kernel, about 8 B per voxel.
 #include "internal.hpp"
 
 namespace nbt {
 
+// Word of padded voxel (X, Y, Z) (border and brick padding: the sentinel).
+__device__ __forceinline__ uint32_t encode_word(const float* __restrict__ prob, const DevMap& m, uint32_t X,
+                                                uint32_t Y, uint32_t Z, float occ_thr, float free_thr,
+                                                bool& any_bad) {
+    if (X == 0 || Y == 0 || Z == 0 || X >= (uint32_t)m.px - 1 || Y >= (uint32_t)m.py - 1 ||
+        Z >= (uint32_t)m.pz - 1)
+        return kSentinel;
+    const float p = prob[((size_t)(Z - 1) * (size_t)m.ny + (Y - 1)) * (size_t)m.nx + (X - 1)];
+    if (!(p >= 0.0f && p <= 1.0f)) {          // also rejects NaN
+        any_bad = true;
+        return kGainOne;
+    }
+    if (p > occ_thr) return __float_as_uint(1.0f - p) | kOccBit;
+    if (p < free_thr) return __float_as_uint(p) & ~kOccBit;    // -0.0 is stored as +0.0
+    return kGainOne;
+}
+
+// One thread per stored word, in storage order (coalesced writes).
 __global__ __launch_bounds__(256) void encode_map_kernel(const float* __restrict__ prob,
                                                          uint32_t* __restrict__ enc, DevMap m,
                                                          float occ_thr, float free_thr,
                                                          unsigned int* __restrict__ bad) {
-    const uint32_t px = (uint32_t)m.px, py = (uint32_t)m.py, pz = (uint32_t)m.pz;
-    const uint32_t total = px * py * pz;
+    const uint32_t total = m.bytes / 4u;
     const uint32_t stride = gridDim.x * blockDim.x;
     bool any_bad = false;
     for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
-        const uint32_t x = idx % px;
-        const uint32_t yz = idx / px;
-        const uint32_t y = yz % py;
-        const uint32_t z = yz / py;
-        uint32_t word;
-        if (x == 0 || y == 0 || z == 0 || x == px - 1 || y == py - 1 || z == pz - 1) {
-            word = kSentinel;
+        uint32_t X, Y, Z;
+        if (m.layout == kLayoutLinear) {
+            X = idx % (uint32_t)m.px;
+            const uint32_t yz = idx / (uint32_t)m.px;
+            Y = yz % (uint32_t)m.py;
+            Z = yz / (uint32_t)m.py;
         } else {
-            const float p = prob[((size_t)(z - 1) * (size_t)m.ny + (y - 1)) * (size_t)m.nx + (x - 1)];
-            if (!(p >= 0.0f && p <= 1.0f)) {          // also rejects NaN
-                any_bad = true;
-                word = kGainOne;
-            } else if (p > occ_thr) {
-                word = __float_as_uint(1.0f - p) | kOccBit;
-            } else if (p < free_thr) {
-                word = __float_as_uint(p) & ~kOccBit;  // -0.0 is stored as +0.0
-            } else {
-                word = kGainOne;
-            }
+            const uint32_t b = idx >> 6, l = idx & 63u;
+            const uint32_t bx = b % (uint32_t)m.nbx, byz = b / (uint32_t)m.nbx;
+            const uint32_t by = byz % (uint32_t)m.nby, bz = byz / (uint32_t)m.nby;
+            X = bx * 4 + (l & 3u);
+            Y = by * 4 + ((l >> 2) & 3u);
+            Z = bz * 4 + (l >> 4);
         }
-        enc[idx] = word;
+        enc[idx] = encode_word(prob, m, X, Y, Z, occ_thr, free_thr, any_bad);
     }
     if (any_bad) atomicOr(bad, 1u);
 }
 
 hipError_t launch_encode_map(const float* prob, uint32_t* enc, const DevMap& m, float occ_thr,
                              float free_thr, unsigned int* bad_flag, hipStream_t s) {
-    const uint64_t total = (uint64_t)m.px * m.py * m.pz;
+    const uint64_t total = m.bytes / 4u;
     uint64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(encode_map_kernel, dim3((unsigned)blocks), dim3(256), 0, s, prob, enc, m,

@@ -194,7 +194,10 @@ int nbt_ig_create_map(nbt_ig_ctx* ctx, const float* prob, int nx, int ny, int nz
     if (!prob || !origin) return fail(NBT_IG_EINVAL, "prob or origin is NULL");
     if (nx < 1 || ny < 1 || nz < 1 || nx > 4096 || ny > 4096 || nz > 4096)
         return fail(NBT_IG_EINVAL, "map dims %dx%dx%d outside [1, 4096]", nx, ny, nz);
-    const uint64_t padded = (uint64_t)(nx + 2) * (ny + 2) * (nz + 2);
+    const int layout = ctx->map_layout;
+    const int nbx = (nx + 2 + 3) / 4, nby = (ny + 2 + 3) / 4, nbz = (nz + 2 + 3) / 4;
+    const uint64_t padded = layout == NBT_IG_LAYOUT_BRICK4 ? (uint64_t)nbx * nby * nbz * 64
+                                                           : (uint64_t)(nx + 2) * (ny + 2) * (nz + 2);
     if (padded >= (1ull << 30))
         return fail(NBT_IG_EUNSUPPORTED, "map %dx%dx%d: padded size must stay below 2^30 voxels", nx, ny, nz);
     if (!finite_pos(voxel_size)) return fail(NBT_IG_EINVAL, "voxel_size must be finite and > 0");
@@ -225,6 +228,8 @@ int nbt_ig_create_map(nbt_ig_ctx* ctx, const float* prob, int nx, int ny, int nz
     dm.bytes = (uint32_t)map->enc_bytes;
     dm.nx = nx; dm.ny = ny; dm.nz = nz;
     dm.px = nx + 2; dm.py = ny + 2; dm.pz = nz + 2;
+    dm.layout = layout;
+    dm.nbx = nbx; dm.nby = nby; dm.nbz = nbz;
     dm.inv_s = 1.0f / voxel_size;
     dm.ox = origin[0]; dm.oy = origin[1]; dm.oz = origin[2];
 
@@ -391,6 +396,28 @@ int nbt_ig_ctx_set_lds_budget(nbt_ig_ctx* ctx, size_t bytes) {
     if (!ctx) return fail(NBT_IG_EINVAL, "ctx is NULL");
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->lds_budget = (bytes == 0 || bytes > ctx->lds_max) ? ctx->lds_max : bytes;
+    return NBT_IG_OK;
+}
+
+int nbt_ig_ctx_set_map_layout(nbt_ig_ctx* ctx, int layout) {
+    if (!ctx) return fail(NBT_IG_EINVAL, "ctx is NULL");
+    if (layout != NBT_IG_LAYOUT_LINEAR && layout != NBT_IG_LAYOUT_BRICK4)
+        return fail(NBT_IG_EINVAL, "unknown map layout %d", layout);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->map_layout = layout;
+    return NBT_IG_OK;
+}
+
+int nbt_ig_ctx_get_map_layout(const nbt_ig_ctx* ctx, int* layout) {
+    if (!ctx || !layout) return fail(NBT_IG_EINVAL, "ctx or output is NULL");
+    *layout = ctx->map_layout;
+    return NBT_IG_OK;
+}
+
+int nbt_ig_map_layout(const nbt_ig_map* map, int* layout) {
+    if (int rc = check_map(map)) return rc;
+    if (!layout) return fail(NBT_IG_EINVAL, "output is NULL");
+    *layout = map->dm.layout;
     return NBT_IG_OK;
 }
 

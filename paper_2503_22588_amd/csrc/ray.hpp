@@ -128,10 +128,6 @@ __device__ __forceinline__ uint32_t load_word(__amdgpu_buffer_rsrc_t rs, uint32_
     return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)byte_off, 0, 0);
 }
 
-__device__ __forceinline__ uint32_t padded_offset(const DevMap& m, int x, int y, int z) {
-    return ((uint32_t)((z + 1) * m.py + (y + 1)) * (uint32_t)m.px + (uint32_t)(x + 1)) * 4u;
-}
-
 __device__ __forceinline__ unsigned long long fnv1a_u32(unsigned long long h, uint32_t v) {
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -149,18 +145,13 @@ enum WalkEnd : int { kEndHit = NBT_IG_RAY_HIT, kEndEnd = NBT_IG_RAY_END, kEndExi
 // Walks one ray.  Per visited voxel the encoded word is gathered and its gain
 // added; the walk stops after an Occupied voxel, on the border sentinel (the
 // previous voxel was the last), or when the next face crossing lies beyond
-// the segment end.  The loop body is straight-line code with a single exit
-// test so that divergent lanes cost one mask update per step.  When TRACK is
-// set the voxel coordinates are kept and visit(x, y, z) runs for every
-// visited voxel.
+// the segment end.  The voxel coordinates are kept and addressed through
+// voxel_offset (either layout); when TRACK is set visit(x, y, z) runs for
+// every visited voxel.
 template <bool TRACK, class Visit>
 __device__ __forceinline__ int walk_ray(const DevMap& m, __amdgpu_buffer_rsrc_t rs, RayState& r,
                                         double& acc, uint32_t& steps, Visit&& visit) {
-    const int dxo = r.sx * 4;
-    const int dyo = r.sy * m.px * 4;
-    const int dzo = r.sz * m.px * m.py * 4;
     const float dtx = r.dtx, dty = r.dty, dtz = r.dtz;
-    uint32_t off = padded_offset(m, r.ix, r.iy, r.iz);
     float tx = r.tx, ty = r.ty, tz = r.tz;
     const float t1 = r.t1;
     const uint32_t guard = (uint32_t)(m.nx + m.ny + m.nz + 3);
@@ -168,7 +159,7 @@ __device__ __forceinline__ int walk_ray(const DevMap& m, __amdgpu_buffer_rsrc_t 
     uint32_t bits;
     float tm;
     for (;;) {
-        bits = load_word(rs, off);
+        bits = load_word(rs, voxel_offset(m, r.ix, r.iy, r.iz));
         const bool sentinel = bits == kSentinel;
         const float g = sentinel ? 0.0f : __uint_as_float(bits & ~kOccBit);
         acc += (double)g;
@@ -181,16 +172,13 @@ __device__ __forceinline__ int walk_ray(const DevMap& m, __amdgpu_buffer_rsrc_t 
         const bool bx = (tx == tm);
         const bool by = !bx && (ty == tm);
         const bool bz = !bx && !by;
-        off += bx ? dxo : (by ? dyo : dzo);
         const float nt = tm + (bx ? dtx : (by ? dty : dtz));
         tx = bx ? nt : tx;
         ty = by ? nt : ty;
         tz = bz ? nt : tz;
-        if constexpr (TRACK) {
-            r.ix += bx ? r.sx : 0;
-            r.iy += by ? r.sy : 0;
-            r.iz += bz ? r.sz : 0;
-        }
+        r.ix += bx ? r.sx : 0;
+        r.iy += by ? r.sy : 0;
+        r.iz += bz ? r.sz : 0;
     }
     steps += n;
     if ((int)bits < 0) return bits == kSentinel ? kEndExit : kEndHit;
@@ -202,14 +190,51 @@ __device__ __forceinline__ int walk_ray(const DevMap& m, __amdgpu_buffer_rsrc_t 
 // lies in 0x80000000..0xBF800000.
 constexpr uint32_t kMarkerMin = 0xBF800001u;
 
+// Per-ray constants of the incremental map offset.  Linear layout: a step on
+// axis a adds d[a] bytes.  Brick layout: a step inside the brick adds d[a]
+// (the in-brick stride), a step across a brick face adds big[a]; the step
+// crosses when the voxel's in-brick coordinate on that axis is 3 (forward)
+// or 0 (backward), i.e. when ((off ^ flip) & mask_a) == 0, with the in-brick
+// x, y, z coordinates in bits 2-3, 4-5, 6-7 of the byte offset and flip
+// holding 3 in the fields of the forward axes.
+struct OffsetSteps {
+    int dx, dy, dz;
+    int bigx, bigy, bigz;
+    uint32_t flip;
+};
+
+template <bool BRICK>
+__device__ __forceinline__ OffsetSteps offset_steps(const DevMap& m, const RayState& r) {
+    OffsetSteps o;
+    if constexpr (!BRICK) {
+        o.dx = r.sx * 4;
+        o.dy = r.sy * m.px * 4;
+        o.dz = r.sz * m.px * m.py * 4;
+        o.bigx = o.bigy = o.bigz = 0;
+        o.flip = 0;
+    } else {
+        o.dx = r.sx * 4;
+        o.dy = r.sy * 16;
+        o.dz = r.sz * 64;
+        o.bigx = r.sx * (256 - 12);
+        o.bigy = r.sy * (256 * m.nbx - 48);
+        o.bigz = r.sz * (256 * m.nbx * m.nby - 192);
+        o.flip = (r.sx > 0 ? 0x0Cu : 0u) | (r.sy > 0 ? 0x30u : 0u) | (r.sz > 0 ? 0xC0u : 0u);
+    }
+    return o;
+}
+
 // One generator step of the pipelined walk: move to the next voxel unless
 // the next face crossing lies beyond the segment end.  Past the end the
 // generator points at offset 0, the sentinel word in the corner of the
-// border, so every later gather reads "stop" without the loaded value ever
-// being inspected here (which would force a wait for it).  Loop invariants
-// are passed by value so that the axis choice stays a register select.
+// border (either layout), so every later gather reads "stop" without the
+// loaded value ever being inspected here (which would force a wait for it).
+// Loop invariants are passed by value so that the axis choice stays a
+// register select.
+template <bool BRICK>
 __device__ __forceinline__ void dda_advance(float& tx, float& ty, float& tz, uint32_t& off,
                                             bool& alive, float t1, int dxo, int dyo, int dzo,
+                                            int bxo, int byo, int bzo, uint32_t flip,
                                             float dtx, float dty, float dtz) {
     const float x = tx, y = ty, z = tz;
     const float tm = fminf(fminf(x, y), z);
@@ -218,7 +243,13 @@ __device__ __forceinline__ void dda_advance(float& tx, float& ty, float& tz, uin
     const bool bx = go && ex;
     const bool by = go && !ex && ey;
     const bool bz = go && !ex && !ey;
-    off = go ? off + (bx ? dxo : (by ? dyo : dzo)) : 0u;
+    int d = bx ? dxo : (by ? dyo : dzo);
+    if constexpr (BRICK) {
+        const uint32_t msk = bx ? 0x0Cu : (by ? 0x30u : 0xC0u);
+        const int big = bx ? bxo : (by ? byo : bzo);
+        d = ((off ^ flip) & msk) == 0u ? big : d;
+    }
+    off = go ? off + (uint32_t)d : 0u;
     const float nt = tm + (bx ? dtx : (by ? dty : dtz));
     tx = bx ? nt : x;
     ty = by ? nt : y;
@@ -234,16 +265,14 @@ __device__ __forceinline__ void dda_advance(float& tx, float& ty, float& tz, uin
 // the generator reads once the segment has ended).  Visits, gains and their
 // order are exactly those of walk_ray; only the reason is not reported, and
 // the visit count only when COUNT is set.  Gathers past a stop are never
-// consumed (and out-of-range ones read 0).
-template <int P, bool COUNT>
+// consumed (and out-of-range ones read 0).  BRICK selects the map layout.
+template <int P, bool COUNT, bool BRICK>
 __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buffer_rsrc_t rs,
                                                    const RayState& r, double& acc, uint32_t& steps) {
-    const int dxo = r.sx * 4;
-    const int dyo = r.sy * m.px * 4;
-    const int dzo = r.sz * m.px * m.py * 4;
+    const OffsetSteps o = offset_steps<BRICK>(m, r);
     const float dtx = r.dtx, dty = r.dty, dtz = r.dtz;
     const float t1 = r.t1;
-    uint32_t off = padded_offset(m, r.ix, r.iy, r.iz);
+    uint32_t off = voxel_offset(m, r.ix, r.iy, r.iz);
     float tx = r.tx, ty = r.ty, tz = r.tz;
     bool alive = true;     // the generator has not yet passed the segment end
 
@@ -251,7 +280,8 @@ __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buf
     w[0] = load_word(rs, off);
 #pragma unroll
     for (int u = 1; u < P; ++u) {
-        dda_advance(tx, ty, tz, off, alive, t1, dxo, dyo, dzo, dtx, dty, dtz);
+        dda_advance<BRICK>(tx, ty, tz, off, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.bigz, o.flip,
+                           dtx, dty, dtz);
         w[u] = load_word(rs, off);
     }
     uint32_t n = 0;
@@ -276,7 +306,8 @@ __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buf
             acc += (double)fabsf(__uint_as_float(xs));
             if constexpr (COUNT) n += take ? 1u : 0u;
             run = run && (int)x >= 0;
-            dda_advance(tx, ty, tz, off, alive, t1, dxo, dyo, dzo, dtx, dty, dtz);
+            dda_advance<BRICK>(tx, ty, tz, off, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.bigz, o.flip,
+                               dtx, dty, dtz);
             w[u] = load_word(rs, off);
         }
         run = run && --budget != 0u;
@@ -287,10 +318,11 @@ __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buf
 // dda_advance plus a second index (a bitset position) that moves with the
 // map offset: by dbx/dby/dbz per step on x/y/z, and stays put once the
 // segment has ended.
+template <bool BRICK>
 __device__ __forceinline__ void dda_advance_idx(float& tx, float& ty, float& tz, uint32_t& off,
-                                                int& idx, bool& alive, float t1, int dxo, int dyo,
-                                                int dzo, int dbx, int dby, int dbz, float dtx,
-                                                float dty, float dtz) {
+                                                int& idx, bool& alive, float t1, int dxo, int dyo, int dzo,
+                                                int bxo, int byo, int bzo, uint32_t flip, int dbx, int dby,
+                                                int dbz, float dtx, float dty, float dtz) {
     const float x = tx, y = ty, z = tz;
     const float tm = fminf(fminf(x, y), z);
     const bool go = alive && !(tm > t1);
@@ -298,7 +330,13 @@ __device__ __forceinline__ void dda_advance_idx(float& tx, float& ty, float& tz,
     const bool bx = go && ex;
     const bool by = go && !ex && ey;
     const bool bz = go && !ex && !ey;
-    off = go ? off + (bx ? dxo : (by ? dyo : dzo)) : 0u;
+    int d = bx ? dxo : (by ? dyo : dzo);
+    if constexpr (BRICK) {
+        const uint32_t msk = bx ? 0x0Cu : (by ? 0x30u : 0xC0u);
+        const int big = bx ? bxo : (by ? byo : bzo);
+        d = ((off ^ flip) & msk) == 0u ? big : d;
+    }
+    off = go ? off + (uint32_t)d : 0u;
     idx = go ? idx + (bx ? dbx : (by ? dby : dbz)) : idx;
     const float nt = tm + (bx ? dtx : (by ? dty : dtz));
     tx = bx ? nt : x;
@@ -318,17 +356,15 @@ __device__ __forceinline__ void dda_advance_idx(float& tx, float& ty, float& tz,
 // voxels is exactly the set visited.  CHECK = false sets every visit with an
 // atomic OR (for bitsets in global memory, where a read could be served by a
 // stale L1 line).  Returns the number of voxels visited.
-template <int P, bool CHECK>
+template <int P, bool CHECK, bool BRICK>
 __device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buffer_rsrc_t rs,
                                                   const RayState& r, int lx, int ly, int lz, int ax,
                                                   int ay, uint32_t nbits, uint32_t* bits) {
-    const int dxo = r.sx * 4;
-    const int dyo = r.sy * m.px * 4;
-    const int dzo = r.sz * m.px * m.py * 4;
+    const OffsetSteps o = offset_steps<BRICK>(m, r);
     const int dbx = r.sx, dby = r.sy * ax, dbz = r.sz * ax * ay;
     const float dtx = r.dtx, dty = r.dty, dtz = r.dtz;
     const float t1 = r.t1;
-    uint32_t off = padded_offset(m, r.ix, r.iy, r.iz);
+    uint32_t off = voxel_offset(m, r.ix, r.iy, r.iz);
     int bidx = ((r.iz - lz) * ay + (r.iy - ly)) * ax + (r.ix - lx);
     float tx = r.tx, ty = r.ty, tz = r.tz;
     const uint32_t guard = (uint32_t)(m.nx + m.ny + m.nz + 3);
@@ -340,7 +376,8 @@ __device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buff
     bi[0] = bidx;
 #pragma unroll
     for (int u = 1; u < P; ++u) {
-        dda_advance_idx(tx, ty, tz, off, bidx, alive, t1, dxo, dyo, dzo, dbx, dby, dbz, dtx, dty, dtz);
+        dda_advance_idx<BRICK>(tx, ty, tz, off, bidx, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.bigz, o.flip,
+                               dbx, dby, dbz, dtx, dty, dtz);
         w[u] = load_word(rs, off);
         bi[u] = bidx;
     }
@@ -364,8 +401,8 @@ __device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buff
             }
             n += take ? 1u : 0u;
             run = run && (int)x >= 0;
-            dda_advance_idx(tx, ty, tz, off, bidx, alive, t1, dxo, dyo, dzo, dbx, dby, dbz, dtx, dty,
-                            dtz);
+            dda_advance_idx<BRICK>(tx, ty, tz, off, bidx, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.bigz, o.flip,
+                               dbx, dby, dbz, dtx, dty, dtz);
             w[u] = load_word(rs, off);
             bi[u] = bidx;
         }

@@ -123,7 +123,10 @@ __global__ __launch_bounds__(WAVES * 64) void traj_union_kernel(
             RayState ray;
             const int st = setup_ray(m, c, pose, i, j, ray);
             if (st == kRayOk) {
-                steps += walk_ray_mark<4, !GLOBAL>(m, rs, ray, b.lx, b.ly, b.lz, b.ax, b.ay, b.nbits, bits);
+                if (m.layout == kLayoutBrick4)
+                    steps += walk_ray_mark<4, !GLOBAL, true>(m, rs, ray, b.lx, b.ly, b.lz, b.ax, b.ay, b.nbits, bits);
+                else
+                    steps += walk_ray_mark<4, !GLOBAL, false>(m, rs, ray, b.lx, b.ly, b.lz, b.ax, b.ay, b.nbits, bits);
             } else if (st == kRayInvalid) {
                 invalid = true;
             }
@@ -146,7 +149,7 @@ __global__ __launch_bounds__(WAVES * 64) void traj_union_kernel(
             const int rem = idx - z * axy;
             const int y = rem / b.ax;
             const int x = rem - y * b.ax;
-            const uint32_t e = load_word(rs, padded_offset(m, b.lx + x, b.ly + y, b.lz + z));
+            const uint32_t e = load_word(rs, voxel_offset(m, b.lx + x, b.ly + y, b.lz + z));
             gain += (double)__uint_as_float(e & ~kOccBit);
             if (e & kOccBit) ++c_occ;
             else if (e == kGainOne) ++c_unk;

@@ -65,10 +65,13 @@ __device__ __forceinline__ void vp_group(const DevMap& m, const CamParams& c,
             RayState ray;
             const int st = setup_ray(m, c, pose, i, j, ray);
             if (st == kRayOk) {
-                if constexpr (DEPTH == 1)
+                if constexpr (DEPTH == 1) {
                     walk_ray<false>(m, rs, ray, acc, steps, [](int, int, int) {});
-                else
-                    walk_ray_pipelined<DEPTH, COUNT>(m, rs, ray, acc, steps);
+                } else if (m.layout == kLayoutBrick4) {      // uniform per workgroup
+                    walk_ray_pipelined<DEPTH, COUNT, true>(m, rs, ray, acc, steps);
+                } else {
+                    walk_ray_pipelined<DEPTH, COUNT, false>(m, rs, ray, acc, steps);
+                }
             } else if (st == kRayInvalid) {
                 invalid = true;
             }

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void patch_kernel(DevMap m, int f, int i0x, in
             for (int dx = 0; dx < f; ++dx) {
                 const int x = i0x + cx * f + dx;
                 if (x < 0 || x >= m.nx) continue;
-                const uint32_t w = load_word(rs, padded_offset(m, x, y, z));
+                const uint32_t w = load_word(rs, voxel_offset(m, x, y, z));
                 occ += (w & kOccBit) ? 1u : 0u;
                 unk += (w == kGainOne) ? 1u : 0u;
             }

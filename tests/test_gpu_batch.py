@@ -28,9 +28,11 @@ def nbt():
     return nbt
 
 
-@pytest.fixture(scope="module")
-def ctx(nbt):
+@pytest.fixture(scope="module", params=[0, 1], ids=["linear", "brick4"])
+def ctx(nbt, request):
+    """Every test of this module runs once per map layout."""
     c = nbt.Context(0)
+    c.set_map_layout(request.param)
     yield c
     c.close()
 

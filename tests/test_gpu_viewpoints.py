@@ -34,9 +34,11 @@ def nbt():
     return nbt
 
 
-@pytest.fixture(scope="module")
-def ctx(nbt):
+@pytest.fixture(scope="module", params=[0, 1], ids=["linear", "brick4"])
+def ctx(nbt, request):
+    """Every test of this module runs once per map layout."""
     c = nbt.Context(0)
+    c.set_map_layout(request.param)
     yield c
     c.close()
 
@@ -280,3 +282,30 @@ def test_argument_errors(nbt, ctx):
     ig, _ = nbt.eval_viewpoints(m, (4, 4, 0.5, 0.5, 1.0), poses)
     torch.cuda.synchronize()
     assert np.isfinite(ig.cpu().numpy()).all()
+
+
+def test_layouts_bit_identical(nbt, ctx):
+    """The two storage orders give the same bits for IG, step counts and ray digests."""
+    import torch
+    w = make_config(1)
+    scene, cam, poses = w.maps[0], w.camera, w.poses[0]
+    _note("layouts agree")
+    out = {}
+    before = ctx.get_map_layout()
+    try:
+        for lay in (nbt.binding.LAYOUT_LINEAR, nbt.binding.LAYOUT_BRICK4):
+            ctx.set_map_layout(lay)
+            m = _map(nbt, ctx, scene)
+            assert m.info()["layout"] == lay
+            ig, st = nbt.eval_viewpoints(m, cam, _dev(poses))
+            d = nbt.trace_rays(m, cam, _dev(poses))
+            torch.cuda.synchronize()
+            out[lay] = (ig.cpu().numpy().view(np.uint32), st.cpu().numpy(), d["hash"].cpu().numpy(),
+                        d["steps"].cpu().numpy())
+            m.close()
+    finally:
+        ctx.set_map_layout(before)
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+    with pytest.raises(nbt.NbtError):
+        ctx.set_map_layout(2)
