@@ -119,7 +119,7 @@ int nbt_ig_ctx_create(int device, nbt_ig_ctx** out);
 void nbt_ig_ctx_destroy(nbt_ig_ctx* ctx);       /* NULL is a no-op; caller syncs its streams first */
 
 /* Storage order of the maps this context creates from now on
- * (NBT_IG_LAYOUT_*; NBT_IG_EINVAL otherwise).  Every call gives the same
+ * (NBT_IG_LAYOUT_*, default NBT_IG_LAYOUT_BRICK4; NBT_IG_EINVAL otherwise).  Every call gives the same
  * results on either; the order only changes how many cache lines one
  * 64-ray gather touches.  The getter reports the current setting;
  * nbt_ig_map_layout the order of an existing map. */
@@ -158,6 +158,13 @@ int nbt_ig_map_check(nbt_ig_map* map, void* stream);
 int nbt_ig_map_info(const nbt_ig_map* map, int* nx, int* ny, int* nz, float* voxel_size,
                     float origin[3], size_t* device_bytes);
 int nbt_ig_map_layout(const nbt_ig_map* map, int* layout);
+
+/* Rewrites an existing map in another storage order (NBT_IG_LAYOUT_*): a new
+ * device buffer is filled from the old one on `stream`, the call synchronises
+ * `stream` and then frees the old buffer.  No evaluation of the map may run
+ * meanwhile (on any stream).  NBT_IG_EINVAL while a batch holds the map (its
+ * descriptor would go stale); a no-op when the map already has the order. */
+int nbt_ig_map_set_layout(nbt_ig_map* map, int layout, void* stream);
 
 /* ---- per-perspective IG (Sec. III, IG calculation) ----------------------------
  * ig_out[p] = g_P of pose p: the mean over its N_E rays of the ray gain g_R
@@ -245,7 +252,8 @@ int nbt_ig_ctx_get_launch(const nbt_ig_ctx* ctx, nbt_ig_launch* launch);
  * (as many as fit on the device at once) pull (perspective, ray-slice) items
  * in map-major order from a device work queue until it is empty.
  *
- * nbt_ig_batch_create: `maps` (HOST array of n_maps handles of this context)
+ * nbt_ig_batch_create: `maps` (HOST array of n_maps handles of this context,
+ * each outliving the batch; their storage order is pinned while it exists)
  * and the camera are fixed for the batch; max_total_viewpoints bounds the
  * perspectives of one run.  The launch shape starts as the context's.
  *
@@ -283,6 +291,14 @@ int nbt_ig_autotune_viewpoints(const nbt_ig_map* map, const nbt_ig_camera* cam, 
 int nbt_ig_batch_autotune(nbt_ig_batch* batch, const uint32_t* vp_offsets, const float* poses,
                           float* ig_out, uint64_t* steps_out, void* stream, nbt_ig_launch* best,
                           float* best_ms);
+
+/* As nbt_ig_autotune_viewpoints, and first the map's storage order: times
+ * nbt_ig_eval_viewpoints on both orders at the context's launch shape, keeps
+ * the map in the faster one (*best_layout, HOST; see nbt_ig_map_set_layout),
+ * then searches the launch shape.  The map must not be held by a batch. */
+int nbt_ig_autotune_map(nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses, uint32_t n,
+                        float* ig_out, uint64_t* steps_out, void* stream, nbt_ig_launch* best,
+                        int* best_layout, float* best_ms);
 
 /* ---- learned IG surrogate ----------------------------------------------------------
  * A small network trained on this library's own exact IG predicts g_P of a

@@ -83,6 +83,9 @@ _sig("nbt_ig_ctx_set_traj_waves", C.c_int, _vp, C.c_int)
 _sig("nbt_ig_ctx_set_map_layout", C.c_int, _vp, C.c_int)
 _sig("nbt_ig_ctx_get_map_layout", C.c_int, _vp, C.POINTER(C.c_int))
 _sig("nbt_ig_map_layout", C.c_int, _vp, C.POINTER(C.c_int))
+_sig("nbt_ig_map_set_layout", C.c_int, _vp, C.c_int, _vp)
+_sig("nbt_ig_autotune_map", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp, _vp, C.POINTER(LaunchT),
+     C.POINTER(C.c_int), C.POINTER(C.c_float))
 _sig("nbt_ig_ctx_get_traj_waves", C.c_int, _vp, C.POINTER(C.c_int))
 _sig("nbt_ig_trace_rays", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp)
 _sig("nbt_ig_trace_paths", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _u32, _u32, _vp, _vp, _vp)
@@ -266,6 +269,10 @@ class Map:
     def check(self, stream=None):
         _check(_lib.nbt_ig_map_check(self.handle, _stream(stream)))
 
+    def set_layout(self, layout, stream=None):
+        """Rewrite the map in another storage order (synchronises the stream)."""
+        _check(_lib.nbt_ig_map_set_layout(self.handle, int(layout), _stream(stream)))
+
     def info(self):
         nx, ny, nz = C.c_int(), C.c_int(), C.c_int()
         vs = C.c_float()
@@ -426,6 +433,22 @@ def autotune_viewpoints(m: Map, cam, poses, ig_out=None, steps_out=None, stream=
                                            _dev_ptr(steps_out, torch.int64, "steps_out"), _stream(stream),
                                            C.byref(l), C.byref(ms)))
     return _launch_dict(l), ms.value
+
+
+def autotune_map(m: Map, cam, poses, ig_out=None, steps_out=None, stream=None):
+    """Pick the faster storage order for the map (it is rewritten in it), then the fastest
+    launch shape (the context keeps it).  Returns (launch, layout, ms)."""
+    torch = _torch()
+    n = poses.shape[0]
+    if ig_out is None:
+        ig_out = torch.empty(n, dtype=torch.float32, device=poses.device)
+    cm = camera(cam)
+    l, lay, ms = LaunchT(), C.c_int(), C.c_float()
+    _check(_lib.nbt_ig_autotune_map(m.handle, C.byref(cm), _dev_ptr(poses, torch.float32, "poses"), n,
+                                    _dev_ptr(ig_out, torch.float32, "ig_out"),
+                                    _dev_ptr(steps_out, torch.int64, "steps_out"), _stream(stream),
+                                    C.byref(l), C.byref(lay), C.byref(ms)))
+    return _launch_dict(l), lay.value, ms.value
 
 
 def _poi(poi):

@@ -8,6 +8,7 @@ using namespace nbt;
 struct nbt_ig_batch {
     nbt_ig_ctx* ctx = nullptr;
     uint32_t n_maps = 0;
+    std::vector<nbt_ig_map*> maps;      // descriptors copied below; their layout is pinned
     DevMap* d_maps = nullptr;           // descriptor table (device)
     CamParams cam{};
     uint32_t capacity = 0;              // max perspectives per run
@@ -207,12 +208,24 @@ int nbt_ig_batch_create(nbt_ig_ctx* ctx, const nbt_ig_map* const* maps, uint32_t
         nbt_ig_batch_destroy(b);
         return rc;
     }
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (uint32_t k = 0; k < n_maps; ++k) {
+            nbt_ig_map* mk = const_cast<nbt_ig_map*>(maps[k]);
+            ++mk->batch_refs;
+            b->maps.push_back(mk);
+        }
+    }
     *out = b;
     return NBT_IG_OK;
 }
 
 void nbt_ig_batch_destroy(nbt_ig_batch* b) {
     if (!b) return;
+    {
+        std::lock_guard<std::mutex> lk(b->ctx->mu);
+        for (nbt_ig_map* mk : b->maps) --mk->batch_refs;
+    }
     DeviceGuard g(b->ctx->device);
     drop_graph(b);
     if (b->d_maps) (void)hipFree(b->d_maps);
@@ -274,6 +287,41 @@ int nbt_ig_autotune_viewpoints(const nbt_ig_map* map, const nbt_ig_camera* cam, 
     *best = from_vp(L);
     *best_ms = ms;
     return NBT_IG_OK;
+}
+
+int nbt_ig_autotune_map(nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses, uint32_t n,
+                        float* ig_out, uint64_t* steps_out, void* stream, nbt_ig_launch* best,
+                        int* best_layout, float* best_ms) {
+    if (int rc = check_map(map)) return rc;
+    if (!best || !best_layout || !best_ms) return fail(NBT_IG_EINVAL, "best, best_layout or best_ms is NULL");
+    if (n == 0) return fail(NBT_IG_EINVAL, "autotuning needs perspectives");
+    hipStream_t s = (hipStream_t)stream;
+    // each layout at the context's current shape, then the shape search on the faster one
+    const int start = map->dm.layout;
+    float ms[2] = {0.0f, 0.0f};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(NBT_IG_EDEVICE, "hipEventCreate failed");
+    int rc = NBT_IG_OK;
+    for (int i = 0; i < 2 && rc == NBT_IG_OK; ++i) {
+        const int lay = i == 0 ? start : 1 - start;
+        rc = nbt_ig_map_set_layout(map, lay, stream);
+        if (rc == NBT_IG_OK) rc = nbt_ig_eval_viewpoints(map, cam, poses, n, ig_out, steps_out, stream);
+        hipError_t e = rc == NBT_IG_OK ? hipEventRecord(e0, s) : hipSuccess;
+        for (int r = 0; r < 2 && rc == NBT_IG_OK && e == hipSuccess; ++r)
+            rc = nbt_ig_eval_viewpoints(map, cam, poses, n, ig_out, steps_out, stream);
+        if (rc == NBT_IG_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+        if (rc == NBT_IG_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+        if (rc == NBT_IG_OK && e == hipSuccess) e = hipEventElapsedTime(&ms[lay], e0, e1);
+        if (rc == NBT_IG_OK && e != hipSuccess) rc = hip_fail(e, "layout timing");
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != NBT_IG_OK) return rc;
+    const int lay = ms[NBT_IG_LAYOUT_BRICK4] < ms[NBT_IG_LAYOUT_LINEAR] ? NBT_IG_LAYOUT_BRICK4 : NBT_IG_LAYOUT_LINEAR;
+    if (int r2 = nbt_ig_map_set_layout(map, lay, stream)) return r2;
+    *best_layout = lay;
+    return nbt_ig_autotune_viewpoints(map, cam, poses, n, ig_out, steps_out, stream, best, best_ms);
 }
 
 int nbt_ig_batch_autotune(nbt_ig_batch* b, const uint32_t* vp_offsets, const float* poses,

@@ -53,7 +53,7 @@ struct nbt_ig_ctx {
     size_t lds_max = 0;             // device limit of LDS per workgroup (bytes)
     size_t lds_budget = 0;          // LDS a trajectory bitset may use (bytes)
     int traj_waves = 8;             // wavefronts per trajectory workgroup (4, 8, 16)
-    int map_layout = NBT_IG_LAYOUT_LINEAR;   // storage order of maps created next
+    int map_layout = NBT_IG_LAYOUT_BRICK4;   // storage order of maps created next
     // trajectory workspace
     nbt::TrajBox* boxes = nullptr;
     uint32_t* over_list = nullptr;
@@ -75,5 +75,6 @@ struct nbt_ig_map {
     float voxel = 0.0f;
     float origin[3] = {0, 0, 0};
     nbt_ig_classify cls{0.5f, 0.5f};
+    int batch_refs = 0;             // batches holding this map's descriptor (under ctx->mu)
 };
 

@@ -97,6 +97,8 @@ struct TrajMeta {
 
 hipError_t launch_encode_map(const float* prob, uint32_t* enc, const DevMap& m, float occ_thr,
                              float free_thr, unsigned int* bad_flag, hipStream_t s);
+// Copies an encoded map into another storage order (dst laid out as dstm).
+hipError_t launch_relayout(const DevMap& src, uint32_t* dst, const DevMap& dstm, hipStream_t s);
 
 hipError_t launch_eval_viewpoints(const DevMap& m, const CamParams& c, const float* poses,
                                   uint32_t n, float* ig_out, unsigned long long* steps_out,

@@ -28,6 +28,23 @@ __device__ __forceinline__ uint32_t encode_word(const float* __restrict__ prob, 
     return kGainOne;
 }
 
+// Padded coordinates of stored word idx.
+__device__ __forceinline__ void word_coords(const DevMap& m, uint32_t idx, uint32_t& X, uint32_t& Y, uint32_t& Z) {
+    if (m.layout == kLayoutLinear) {
+        X = idx % (uint32_t)m.px;
+        const uint32_t yz = idx / (uint32_t)m.px;
+        Y = yz % (uint32_t)m.py;
+        Z = yz / (uint32_t)m.py;
+    } else {
+        const uint32_t b = idx >> 6, l = idx & 63u;
+        const uint32_t bx = b % (uint32_t)m.nbx, byz = b / (uint32_t)m.nbx;
+        const uint32_t by = byz % (uint32_t)m.nby, bz = byz / (uint32_t)m.nby;
+        X = bx * 4 + (l & 3u);
+        Y = by * 4 + ((l >> 2) & 3u);
+        Z = bz * 4 + (l >> 4);
+    }
+}
+
 // One thread per stored word, in storage order (coalesced writes).
 __global__ __launch_bounds__(256) void encode_map_kernel(const float* __restrict__ prob,
                                                          uint32_t* __restrict__ enc, DevMap m,
@@ -38,22 +55,34 @@ __global__ __launch_bounds__(256) void encode_map_kernel(const float* __restrict
     bool any_bad = false;
     for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
         uint32_t X, Y, Z;
-        if (m.layout == kLayoutLinear) {
-            X = idx % (uint32_t)m.px;
-            const uint32_t yz = idx / (uint32_t)m.px;
-            Y = yz % (uint32_t)m.py;
-            Z = yz / (uint32_t)m.py;
-        } else {
-            const uint32_t b = idx >> 6, l = idx & 63u;
-            const uint32_t bx = b % (uint32_t)m.nbx, byz = b / (uint32_t)m.nbx;
-            const uint32_t by = byz % (uint32_t)m.nby, bz = byz / (uint32_t)m.nby;
-            X = bx * 4 + (l & 3u);
-            Y = by * 4 + ((l >> 2) & 3u);
-            Z = bz * 4 + (l >> 4);
-        }
+        word_coords(m, idx, X, Y, Z);
         enc[idx] = encode_word(prob, m, X, Y, Z, occ_thr, free_thr, any_bad);
     }
     if (any_bad) atomicOr(bad, 1u);
+}
+
+// One thread per destination word: the word of the same padded voxel in the
+// source order (the sentinel for the padding of whole bricks).
+__global__ __launch_bounds__(256) void relayout_kernel(const uint32_t* __restrict__ src, DevMap sm,
+                                                       uint32_t* __restrict__ dst, DevMap dm) {
+    const uint32_t total = dm.bytes / 4u;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
+        uint32_t X, Y, Z;
+        word_coords(dm, idx, X, Y, Z);
+        uint32_t w = kSentinel;
+        if (X < (uint32_t)dm.px && Y < (uint32_t)dm.py && Z < (uint32_t)dm.pz)
+            w = src[voxel_offset(sm, (int)X - 1, (int)Y - 1, (int)Z - 1) / 4u];
+        dst[idx] = w;
+    }
+}
+
+hipError_t launch_relayout(const DevMap& src, uint32_t* dst, const DevMap& dstm, hipStream_t s) {
+    const uint64_t total = dstm.bytes / 4u;
+    uint64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(relayout_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src.enc, src, dst, dstm);
+    return hipGetLastError();
 }
 
 hipError_t launch_encode_map(const float* prob, uint32_t* enc, const DevMap& m, float occ_thr,

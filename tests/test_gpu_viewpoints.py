@@ -309,3 +309,43 @@ def test_layouts_bit_identical(nbt, ctx):
         assert np.array_equal(a, b)
     with pytest.raises(nbt.NbtError):
         ctx.set_map_layout(2)
+
+
+def test_relayout_and_layout_autotune(nbt, ctx):
+    """Rewriting a map in the other order keeps every result bit; the layout autotuner leaves
+    the map in one of the two orders with the same results; a batch pins the order."""
+    import torch
+    w = make_config(1)
+    scene, cam, poses = w.maps[0], w.camera, w.poses[0]
+    _note("relayout")
+    m = _map(nbt, ctx, scene)
+    dp = _dev(poses)
+    ig0, st0 = nbt.eval_viewpoints(m, cam, dp)
+    d0 = nbt.trace_rays(m, cam, dp)
+    torch.cuda.synchronize()
+    start = m.info()["layout"]
+    for lay in (1 - start, start, 1 - start):
+        m.set_layout(lay)
+        assert m.info()["layout"] == lay
+        ig, st = nbt.eval_viewpoints(m, cam, dp)
+        d = nbt.trace_rays(m, cam, dp)
+        torch.cuda.synchronize()
+        assert np.array_equal(ig.cpu().numpy().view(np.uint32), ig0.cpu().numpy().view(np.uint32))
+        assert np.array_equal(st.cpu().numpy(), st0.cpu().numpy())
+        assert np.array_equal(d["hash"].cpu().numpy(), d0["hash"].cpu().numpy())
+    before = ctx.get_launch()
+    try:
+        launch, lay, ms = nbt.autotune_map(m, cam, dp)
+        assert lay in (0, 1) and m.info()["layout"] == lay and ms > 0
+        ig, st = nbt.eval_viewpoints(m, cam, dp)
+        torch.cuda.synchronize()
+        assert np.array_equal(ig.cpu().numpy().view(np.uint32), ig0.cpu().numpy().view(np.uint32))
+    finally:
+        ctx.set_launch(*[before[k] for k in ("waves_per_group", "tile_w_log2", "tiles_per_wave",
+                                             "xcd_remap", "pipeline_depth")])
+    b = nbt.Batch(ctx, [m], cam, 64)
+    with pytest.raises(nbt.NbtError):
+        m.set_layout(1 - m.info()["layout"])
+    b.close()
+    m.set_layout(1 - m.info()["layout"])        # allowed again once the batch is gone
+    m.close()
