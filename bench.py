@@ -173,8 +173,10 @@ def extra_batch(nbt, ctx, reps):
     return res
 
 
-def extra_surrogate(nbt, ctx, n_maps=8, n_cand=65536, k_rescore=256, k=10):
-    """Surrogate-pruned selection vs plain raycasting on held-out config-1-family maps."""
+def extra_surrogate(nbt, ctx, n_maps=16, n_cand=65536, k_rescores=(64, 256, 1024), k=10, target=0.95):
+    """Surrogate-pruned selection vs plain raycasting on held-out config-1-family maps, at
+    several rescoring budgets; the headline operating point is the smallest budget whose
+    top-10 agreement with exact IG reaches `target`."""
     import numpy as np
     import torch
     from workloads import poses_shell, scene_spheres
@@ -185,7 +187,8 @@ def extra_surrogate(nbt, ctx, n_maps=8, n_cand=65536, k_rescore=256, k=10):
     blob = open(path, "rb").read()
     sur = nbt.Surrogate(ctx, blob)
     stream = torch.cuda.current_stream()
-    agree, ratio, nmae, t_plain, t_sur = [], [], [], [], []
+    t_plain, nmae = [], []
+    per = {kr: {"agree": [], "ratio": [], "ms": []} for kr in k_rescores}
     for i in range(n_maps):
         seed = 22588 + 5000 + 100000 + i                     # held out from training
         sc = scene_spheres(n=64, voxel=0.05, n_spheres=10 + seed % 31, seed=seed)
@@ -195,28 +198,39 @@ def extra_surrogate(nbt, ctx, n_maps=8, n_cand=65536, k_rescore=256, k=10):
         dp = torch.from_numpy(poses_shell(poi.astype(np.float64), 0.4, 1.3, n_cand, seed + 500)).cuda()
         ig = torch.empty(n_cand, device="cuda")
         t_plain.append(_timed(lambda: nbt.eval_viewpoints(m, CAM1, dp, ig_out=ig, want_steps=False), 3, stream))
-        out = {}
-
-        def sel():
-            out["r"] = sur.select(m, CAM1, poi, dp, k_rescore=k_rescore, k=k)
-
-        t_sur.append(_timed(sel, 5, stream))
-        pred = sur.predict(m, poi, dp)
-        torch.cuda.synchronize()
         ex = ig.cpu().numpy()
         top = set(np.lexsort((np.arange(n_cand), -ex))[:k].tolist())
-        agree.append(len(top & set(out["r"][0].cpu().numpy().tolist())) / k)
-        ratio.append(float(out["r"][1].cpu().numpy()[0]) / float(ex.max()))
+        for kr in k_rescores:
+            out = {}
+
+            def sel():
+                out["r"] = sur.select(m, CAM1, poi, dp, k_rescore=kr, k=k)
+
+            per[kr]["ms"].append(_timed(sel, 5, stream))
+            per[kr]["agree"].append(len(top & set(out["r"][0].cpu().numpy().tolist())) / k)
+            per[kr]["ratio"].append(float(out["r"][1].cpu().numpy()[0]) / float(ex.max()))
+        pred = sur.predict(m, poi, dp)
+        torch.cuda.synchronize()
         nmae.append(float(np.mean(np.abs(pred.cpu().numpy() - ex)) / np.mean(ex)))
         m.close()
     sur.close()
-    tp, ts = float(np.mean(t_plain)), float(np.mean(t_sur))
+    tp = float(np.mean(t_plain))
+    points = []
+    for kr in k_rescores:
+        ts = float(np.mean(per[kr]["ms"]))
+        points.append({"k_rescore": kr, "surrogate_ms": ts, "surrogate_evals_per_s": n_cand / (ts * 1e-3),
+                       "speedup": tp / ts, "top10_agreement": float(np.mean(per[kr]["agree"])),
+                       "best_ig_ratio": float(np.mean(per[kr]["ratio"])),
+                       "worst_best_ig_ratio": float(np.min(per[kr]["ratio"]))})
+    ok = [p for p in points if p["top10_agreement"] >= target]
+    head = ok[0] if ok else points[-1]
     return {"workload": f"{n_maps} held-out 64^3 sphere maps, {n_cand} candidates in the 0.4-1.3 m shell, "
-                        f"64x48 rays; top-{k_rescore} rescored exactly, top-{k} kept",
-            "surrogate_evals_per_s": n_cand / (ts * 1e-3), "plain_evals_per_s": n_cand / (tp * 1e-3),
-            "speedup": tp / ts, "surrogate_ms": ts, "plain_ms": tp,
-            "top10_agreement": float(np.mean(agree)), "per_map_agreement": agree,
-            "best_ig_ratio": float(np.mean(ratio)), "worst_best_ig_ratio": float(np.min(ratio)),
+                        f"64x48 rays; top-k_rescore rescored exactly, top-{k} kept",
+            "plain_ms": tp, "plain_evals_per_s": n_cand / (tp * 1e-3),
+            "k_rescore": head["k_rescore"], "surrogate_ms": head["surrogate_ms"],
+            "surrogate_evals_per_s": head["surrogate_evals_per_s"], "speedup": head["speedup"],
+            "top10_agreement": head["top10_agreement"], "best_ig_ratio": head["best_ig_ratio"],
+            "agreement_target": target, "operating_points": points,
             "prediction_nmae": float(np.mean(nmae))}
 
 
@@ -433,7 +447,7 @@ def main():
         result["binding_unit"] = {
             "unit": "TA (vector-memory address path)",
             "ta_busy_frac": float(counters["TA busy fraction"]),
-            "valu_busy_frac": float(counters["VALU busy fraction"]),
+            "valu_instr_per_cu_cycle": float(counters["VALU per CU-cycle"]),
             "tcp_accesses_per_gather": float(counters["L1 accesses per gather"]),
             "source": COUNTERS_PROFILE,
         }
