@@ -171,12 +171,14 @@ def evaluate(nbt, ctx, cam, blob, seeds, n_cand=65536, k_rescores=(64, 256, 1024
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default="surrogate.nbts")
-    ap.add_argument("--scenes", type=int, default=4096)
+    ap.add_argument("--scenes", type=int, default=12288)
     ap.add_argument("--per-scene", type=int, default=1024)
-    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed-base", type=int, default=22588 + 5000)
+    ap.add_argument("--listwise", type=float, default=1.0, help="weight of the listwise ranking term")
+    ap.add_argument("--tau", type=float, default=0.05, help="softmax temperature of the listwise term")
     ap.add_argument("--log", default=None)
     ap.add_argument("--eval-maps", type=int, default=16, help="held-out maps for the quality report")
     args = ap.parse_args()
@@ -231,6 +233,11 @@ def main():
             dp = torch.gather(pred, 1, pi) - torch.gather(pred, 1, pj)
             rank = torch.relu(0.01 - torch.sign(dy) * dp)[dy.abs() > 0.01].mean()
             loss = loss + 0.5 * torch.nan_to_num(rank)
+            if args.listwise > 0:
+                # listwise term: cross-entropy between the softmax of the labels and of the
+                # predictions over each scene's candidates, which weighs the top of the list
+                tgt = torch.softmax(y / args.tau, dim=1)
+                loss = loss - args.listwise * (tgt * torch.log_softmax(pred / args.tau, dim=1)).sum(1).mean()
             opt.zero_grad(set_to_none=True)
             loss.backward()
             opt.step()
