@@ -349,3 +349,41 @@ def test_relayout_and_layout_autotune(nbt, ctx):
     b.close()
     m.set_layout(1 - m.info()["layout"])        # allowed again once the batch is gone
     m.close()
+
+
+def test_update_map_and_check(nbt, ctx):
+    """Re-encoding a resident map in place from new probabilities gives the oracle's results on
+    the new map; an update that meets NaN or values outside [0, 1] is reported by the next
+    check (and only then), and a clean update afterwards checks clean."""
+    import torch
+    _note("map update + check")
+    a = scene_spheres(n=(40, 36, 44), voxel=0.05, n_spheres=12, seed=311)
+    b = scene_spheres(n=(40, 36, 44), voxel=0.05, n_spheres=25, seed=312)
+    cam = Camera(37, 23, 60, 45, 1.5)
+    poses = poses_sphere(a.poi, 0.6, 12, seed=313)
+    m = nbt.Map(ctx, a.P, a.voxel, a.origin)
+    dp = _dev(poses)
+    m.update(_dev(b.P))
+    ig, st = nbt.eval_viewpoints(m, cam, dp)
+    torch.cuda.synchronize()
+    m.check()
+    ig_ref, st_ref = oracle.eval_viewpoints(b, cam, poses)
+    assert np.array_equal(st.cpu().numpy().view(np.uint64), st_ref)
+    rel, nan_ok = _ig_close(ig.cpu().numpy(), ig_ref)
+    assert nan_ok and rel <= IG_RTOL
+    bad = b.P.copy()
+    bad[3, 4, 5] = np.nan
+    bad[7, 8, 9] = 1.5
+    m.update(_dev(bad))
+    with pytest.raises(nbt.NbtError) as e:
+        m.check()
+    assert e.value.status == nbt.binding.EINVAL
+    m.update(_dev(a.P))
+    m.check()                                   # the flag was cleared by the failing check
+    ig2, st2 = nbt.eval_viewpoints(m, cam, dp)
+    torch.cuda.synchronize()
+    ig_a, st_a = oracle.eval_viewpoints(a, cam, poses)
+    assert np.array_equal(st2.cpu().numpy().view(np.uint64), st_a)
+    with pytest.raises(ValueError):
+        m.update(_dev(a.P[:-1]))
+    m.close()
