@@ -200,11 +200,13 @@ def extra_surrogate(nbt, ctx, n_maps=16, n_cand=65536, k_rescores=(64, 256, 1024
         t_plain.append(_timed(lambda: nbt.eval_viewpoints(m, CAM1, dp, ig_out=ig, want_steps=False), 3, stream))
         ex = ig.cpu().numpy()
         top = set(np.lexsort((np.arange(n_cand), -ex))[:k].tolist())
+        sel_idx = torch.empty(k, dtype=torch.int32, device="cuda")
+        sel_ig = torch.empty(k, device="cuda")
         for kr in k_rescores:
             out = {}
 
             def sel():
-                out["r"] = sur.select(m, CAM1, poi, dp, k_rescore=kr, k=k)
+                out["r"] = sur.select(m, CAM1, poi, dp, k_rescore=kr, k=k, idx_out=sel_idx, ig_out=sel_ig)
 
             per[kr]["ms"].append(_timed(sel, 5, stream))
             per[kr]["agree"].append(len(top & set(out["r"][0].cpu().numpy().tolist())) / k)

@@ -116,7 +116,8 @@ typedef struct {
  * Fails with NBT_IG_EUNSUPPORTED when the device is not gfx950.
  */
 int nbt_ig_ctx_create(int device, nbt_ig_ctx** out);
-void nbt_ig_ctx_destroy(nbt_ig_ctx* ctx);       /* NULL is a no-op; caller syncs its streams first */
+void nbt_ig_ctx_destroy(nbt_ig_ctx* ctx);       /* NULL is a no-op; caller syncs its streams and destroys
+                                                   the context's batches, surrogates and maps first */
 
 /* Storage order of the maps this context creates from now on
  * (NBT_IG_LAYOUT_*, default NBT_IG_LAYOUT_BRICK4; NBT_IG_EINVAL otherwise).  Every call gives the same

@@ -11,6 +11,7 @@ back to another implementation silently.
 from __future__ import annotations
 
 import ctypes as C
+import weakref
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -184,6 +185,7 @@ class Context:
         _check(_lib.nbt_ig_ctx_create(int(device), C.byref(h)))
         self.handle = h
         self.device = int(device)
+        self._children = weakref.WeakSet()     # maps, batches and surrogates of this context
 
     def set_launch(self, waves_per_group=8, tile_w_log2=3, tiles_per_wave=0, xcd_remap=0, pipeline_depth=0):
         _check(_lib.nbt_ig_ctx_set_launch(self.handle, C.byref(LaunchT(waves_per_group, tile_w_log2,
@@ -223,7 +225,13 @@ class Context:
         return {"cu_count": cu.value, "lds_per_group": lds.value, "lds_budget": budget.value}
 
     def close(self):
+        """Destroys the context's batches, surrogates and maps still open, then the context."""
         if self.handle:
+            kids = list(self._children)
+            for kind in (Batch, Surrogate, Map):
+                for obj in kids:
+                    if isinstance(obj, kind):
+                        obj.close()
             _lib.nbt_ig_ctx_destroy(self.handle)
             self.handle = _vp()
 
@@ -253,9 +261,11 @@ class Map:
         cls = ClassifyT(float(thresholds[0]), float(thresholds[1]))
         h = _vp()
         self.ctx = ctx
+        self.handle = _vp()
         _check(_lib.nbt_ig_create_map(ctx.handle, C.c_void_p(prob.data_ptr()), nx, ny, nz, float(voxel),
                                       org, C.byref(cls), _stream(stream), C.byref(h)))
         self.handle = h
+        ctx._children.add(self)
         self.dims = (nx, ny, nz)
         self.voxel = float(voxel)
 
@@ -286,9 +296,9 @@ class Map:
                 "device_bytes": nb.value, "layout": lay.value}
 
     def close(self):
-        if self.handle:
+        if self.handle and self.ctx.handle:
             _lib.nbt_ig_destroy_map(self.handle)
-            self.handle = _vp()
+        self.handle = _vp()
 
     def __del__(self):
         try:
@@ -371,6 +381,8 @@ class Batch:
     """Many maps, one persistent hipGraph-launched evaluation (nbt_ig_batch)."""
 
     def __init__(self, ctx: Context, maps, cam, max_total_viewpoints: int):
+        self.ctx = ctx
+        self.handle = _vp()
         arr = (_vp * len(maps))(*[m.handle for m in maps])
         h = _vp()
         self._cam = camera(cam)
@@ -378,7 +390,7 @@ class Batch:
                                         int(max_total_viewpoints), C.byref(h)))
         self.handle = h
         self.maps = list(maps)          # keep the maps alive
-        self.ctx = ctx
+        ctx._children.add(self)
 
     def run(self, vp_offsets, poses, ig_out, steps_out=None, stream=None):
         torch = _torch()
@@ -409,9 +421,9 @@ class Batch:
         return _launch_dict(l), ms.value
 
     def close(self):
-        if self.handle:
+        if self.handle and self.ctx.handle:
             _lib.nbt_ig_batch_destroy(self.handle)
-            self.handle = _vp()
+        self.handle = _vp()
 
     def __del__(self):
         try:
@@ -468,11 +480,13 @@ class Surrogate:
     """The learned IG surrogate (nbt_ig_surrogate); `weights` is the packed blob (bytes)."""
 
     def __init__(self, ctx: Context, weights: bytes):
+        self.ctx = ctx
+        self.handle = _vp()
         h = _vp()
         buf = C.create_string_buffer(bytes(weights), len(weights))
         _check(_lib.nbt_ig_surrogate_create(ctx.handle, C.cast(buf, C.c_void_p), len(weights), C.byref(h)))
         self.handle = h
-        self.ctx = ctx
+        ctx._children.add(self)
 
     def predict(self, m: Map, poi, poses, pred=None, stream=None):
         torch = _torch()
@@ -483,10 +497,14 @@ class Surrogate:
                                              n, _dev_ptr(pred, torch.float32, "pred"), _stream(stream)))
         return pred
 
-    def select(self, m: Map, cam, poi, poses, k_rescore=256, k=10, stream=None):
+    def select(self, m: Map, cam, poi, poses, k_rescore=256, k=10, stream=None, idx_out=None, ig_out=None):
+        """Best k of the candidates: the surrogate's k_rescore best, rescored exactly (into
+        idx_out / ig_out when given)."""
         torch = _torch()
-        idx = torch.empty(k, dtype=torch.int32, device=poses.device)
-        ig = torch.empty(k, dtype=torch.float32, device=poses.device)
+        idx = idx_out if idx_out is not None else torch.empty(k, dtype=torch.int32, device=poses.device)
+        ig = ig_out if ig_out is not None else torch.empty(k, dtype=torch.float32, device=poses.device)
+        if idx.numel() < k or ig.numel() < k:
+            raise ValueError("idx_out and ig_out need k elements")
         cm = camera(cam)
         _check(_lib.nbt_ig_surrogate_select(self.handle, m.handle, C.byref(cm), _poi(poi),
                                             _dev_ptr(poses, torch.float32, "poses"), poses.shape[0], int(k_rescore),
@@ -503,9 +521,9 @@ class Surrogate:
         return patch, feat
 
     def close(self):
-        if self.handle:
+        if self.handle and self.ctx.handle:
             _lib.nbt_ig_surrogate_destroy(self.handle)
-            self.handle = _vp()
+        self.handle = _vp()
 
     def __del__(self):
         try:

@@ -192,3 +192,32 @@ def test_trained_weights_parity_and_quality(nbt, ctx):
     sur.close()
     assert min(ratios) >= 0.9 and np.mean(ratios) >= 0.97, ratios
     assert np.mean(agree) >= 0.6, agree
+
+
+def test_select_repeats_are_identical(nbt, ctx, setup):
+    """Repeated selections into the same output buffers, with other work on the surrogate's and
+    the context's buffers and synchronisations in between, give identical bits; a smaller k
+    gives the head of the same ranking."""
+    import torch
+    sc, poi, blob, sur, m = setup
+    _note("surrogate select repeats")
+    cam = make_config(1).camera
+    poses = _dev(poses_shell(poi.astype(np.float64), 0.4, 1.3, 6000, seed=707))
+    other = _dev(poses_shell(poi.astype(np.float64), 0.4, 1.3, 3000, seed=708))
+    idx = torch.empty(10, dtype=torch.int32, device="cuda")
+    ig = torch.empty(10, device="cuda")
+    first = None
+    for rep in range(6):
+        i, g = sur.select(m, cam, poi, poses, k_rescore=128, k=10, idx_out=idx, ig_out=ig)
+        torch.cuda.synchronize()
+        got = (i.cpu().numpy().copy(), g.cpu().numpy().view(np.uint32).copy())
+        if first is None:
+            first = got
+        assert np.array_equal(got[0], first[0]) and np.array_equal(got[1], first[1]), rep
+        # other work between the calls, on the buffers a selection uses
+        sur.predict(m, poi, other)
+        nbt.eval_viewpoints(m, cam, other)
+        torch.cuda.synchronize()
+    i2, g2 = sur.select(m, cam, poi, poses, k_rescore=128, k=5, idx_out=idx[:5], ig_out=ig[:5])
+    torch.cuda.synchronize()
+    assert np.array_equal(i2.cpu().numpy(), first[0][:5])
