@@ -293,6 +293,15 @@ int nbt_ig_batch_autotune(nbt_ig_batch* batch, const uint32_t* vp_offsets, const
                           float* ig_out, uint64_t* steps_out, void* stream, nbt_ig_launch* best,
                           float* best_ms);
 
+/* Chooses the storage order of the batch's maps (all alike): times the batch
+ * in both orders at its current launch shape, leaves the maps in the faster
+ * one (*best_layout, HOST; mean ms per run in *best_ms) and updates the
+ * batch.  Synchronises `stream`; no other work may use the maps meanwhile.
+ * NBT_IG_EINVAL when another batch holds one of the maps too. */
+int nbt_ig_batch_autotune_layout(nbt_ig_batch* batch, const uint32_t* vp_offsets, const float* poses,
+                                 float* ig_out, uint64_t* steps_out, void* stream, int* best_layout,
+                                 float* best_ms);
+
 /* As nbt_ig_autotune_viewpoints, and first the map's storage order: times
  * nbt_ig_eval_viewpoints on both orders at the context's launch shape, keeps
  * the map in the faster one (*best_layout, HOST; see nbt_ig_map_set_layout),

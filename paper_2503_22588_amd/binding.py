@@ -100,6 +100,7 @@ _sig("nbt_ig_batch_get_launch", C.c_int, _vp, C.POINTER(LaunchT), C.POINTER(_u32
 _sig("nbt_ig_autotune_viewpoints", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp, _vp,
      C.POINTER(LaunchT), C.POINTER(C.c_float))
 _sig("nbt_ig_batch_autotune", C.c_int, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(LaunchT), C.POINTER(C.c_float))
+_sig("nbt_ig_batch_autotune_layout", C.c_int, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_int), C.POINTER(C.c_float))
 _sig("nbt_ig_surrogate_create", C.c_int, _vp, C.c_void_p, C.c_size_t, C.POINTER(_vp))
 _sig("nbt_ig_surrogate_destroy", None, _vp)
 _sig("nbt_ig_surrogate_predict", C.c_int, _vp, _vp, C.POINTER(C.c_float), _vp, _u32, _vp, _vp)
@@ -419,6 +420,17 @@ class Batch:
                                           _dev_ptr(steps_out, torch.int64, "steps_out"), _stream(stream),
                                           C.byref(l), C.byref(ms)))
         return _launch_dict(l), ms.value
+
+    def autotune_layout(self, vp_offsets, poses, ig_out, steps_out=None, stream=None):
+        """Put all maps of the batch in the faster storage order; returns (layout, ms)."""
+        torch = _torch()
+        lay, ms = C.c_int(), C.c_float()
+        _check(_lib.nbt_ig_batch_autotune_layout(self.handle, _dev_ptr(vp_offsets, torch.int32, "vp_offsets"),
+                                                 _dev_ptr(poses, torch.float32, "poses"),
+                                                 _dev_ptr(ig_out, torch.float32, "ig_out"),
+                                                 _dev_ptr(steps_out, torch.int64, "steps_out"), _stream(stream),
+                                                 C.byref(lay), C.byref(ms)))
+        return lay.value, ms.value
 
     def close(self):
         if self.handle and self.ctx.handle:

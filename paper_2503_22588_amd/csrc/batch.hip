@@ -289,6 +289,58 @@ int nbt_ig_autotune_viewpoints(const nbt_ig_map* map, const nbt_ig_camera* cam, 
     return NBT_IG_OK;
 }
 
+int nbt_ig_batch_autotune_layout(nbt_ig_batch* b, const uint32_t* vp_offsets, const float* poses,
+                                 float* ig_out, uint64_t* steps_out, void* stream, int* best_layout,
+                                 float* best_ms) {
+    if (!b || !best_layout || !best_ms) return fail(NBT_IG_EINVAL, "batch, best_layout or best_ms is NULL");
+    {
+        std::lock_guard<std::mutex> lk(b->ctx->mu);
+        for (nbt_ig_map* mk : b->maps)
+            if (mk->batch_refs > 1) return fail(NBT_IG_EINVAL, "a map of this batch is held by another batch too");
+    }
+    DeviceGuard g(b->ctx->device);
+    if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", b->ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    // every map in one order, then the descriptor table follows and the graph is rebuilt
+    auto apply = [&](int lay) -> int {
+        std::vector<DevMap> table(b->n_maps);
+        for (uint32_t k = 0; k < b->n_maps; ++k) {
+            if (int rc = relayout_map(b->maps[k], lay, s)) return rc;
+            table[k] = b->maps[k]->dm;
+        }
+        hipError_t e = hipMemcpy(b->d_maps, table.data(), b->n_maps * sizeof(DevMap), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "batch descriptor table");
+        drop_graph(b);
+        return NBT_IG_OK;
+    };
+    const int start = b->maps.empty() ? NBT_IG_LAYOUT_LINEAR : b->maps[0]->dm.layout;
+    float ms[2] = {0.0f, 0.0f};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(NBT_IG_EDEVICE, "hipEventCreate failed");
+    int rc = NBT_IG_OK;
+    for (int i = 0; i < 2 && rc == NBT_IG_OK; ++i) {
+        const int lay = i == 0 ? start : 1 - start;
+        rc = apply(lay);
+        if (rc == NBT_IG_OK) rc = nbt_ig_batch_run(b, vp_offsets, poses, ig_out, steps_out, stream);
+        hipError_t e = rc == NBT_IG_OK ? hipEventRecord(e0, s) : hipSuccess;
+        for (int r = 0; r < 3 && rc == NBT_IG_OK && e == hipSuccess; ++r)
+            rc = nbt_ig_batch_run(b, vp_offsets, poses, ig_out, steps_out, stream);
+        if (rc == NBT_IG_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+        if (rc == NBT_IG_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+        if (rc == NBT_IG_OK && e == hipSuccess) e = hipEventElapsedTime(&ms[lay], e0, e1);
+        if (rc == NBT_IG_OK && e != hipSuccess) rc = hip_fail(e, "layout timing");
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != NBT_IG_OK) return rc;
+    const int lay = ms[NBT_IG_LAYOUT_BRICK4] < ms[NBT_IG_LAYOUT_LINEAR] ? NBT_IG_LAYOUT_BRICK4 : NBT_IG_LAYOUT_LINEAR;
+    if (int r2 = apply(lay)) return r2;
+    *best_layout = lay;
+    *best_ms = ms[lay] / 3.0f;
+    return NBT_IG_OK;
+}
+
 int nbt_ig_autotune_map(nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses, uint32_t n,
                         float* ig_out, uint64_t* steps_out, void* stream, nbt_ig_launch* best,
                         int* best_layout, float* best_ms) {

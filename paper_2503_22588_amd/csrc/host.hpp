@@ -78,3 +78,6 @@ struct nbt_ig_map {
     int batch_refs = 0;             // batches holding this map's descriptor (under ctx->mu)
 };
 
+// Rewrites an encoded map in another storage order (synchronises s); callers
+// check that no batch still holds the map's old descriptor.
+int relayout_map(nbt_ig_map* map, int layout, hipStream_t s);

@@ -124,6 +124,34 @@ int check_map(const nbt_ig_map* map) {
 
 // ---------------------------------------------------------------- API -------
 
+// Rewrites the map's words in `layout` order (no check of who holds the map).
+int relayout_map(nbt_ig_map* map, int layout, hipStream_t s) {
+    if (map->dm.layout == layout) return NBT_IG_OK;
+    DeviceGuard g(map->ctx->device);
+    if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", map->ctx->device);
+    DevMap nd = map->dm;
+    nd.layout = layout;
+    const uint64_t words = layout == NBT_IG_LAYOUT_BRICK4 ? (uint64_t)nd.nbx * nd.nby * nd.nbz * 64
+                                                          : (uint64_t)nd.px * nd.py * nd.pz;
+    if (words >= (1ull << 30)) return fail(NBT_IG_EUNSUPPORTED, "map too large for this layout");
+    uint32_t* enc = nullptr;
+    hipError_t e = hipMalloc(&enc, words * 4);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(map)");
+    nd.enc = enc;
+    nd.bytes = (uint32_t)(words * 4);
+    e = launch_relayout(map->dm, enc, nd, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);     // the old words are read until here
+    if (e != hipSuccess) {
+        (void)hipFree(enc);
+        return hip_fail(e, "relayout_kernel");
+    }
+    (void)hipFree(map->enc);
+    map->enc = enc;
+    map->enc_bytes = words * 4;
+    map->dm = nd;
+    return NBT_IG_OK;
+}
+
 extern "C" {
 
 int nbt_ig_abi_version(void) { return NBT_IG_ABI_VERSION; }
@@ -418,38 +446,13 @@ int nbt_ig_map_set_layout(nbt_ig_map* map, int layout, void* stream) {
     if (int rc = check_map(map)) return rc;
     if (layout != NBT_IG_LAYOUT_LINEAR && layout != NBT_IG_LAYOUT_BRICK4)
         return fail(NBT_IG_EINVAL, "unknown map layout %d", layout);
-    nbt_ig_ctx* ctx = map->ctx;
     {
-        std::lock_guard<std::mutex> lk(ctx->mu);
+        std::lock_guard<std::mutex> lk(map->ctx->mu);
         if (map->batch_refs > 0)
             return fail(NBT_IG_EINVAL, "the map is held by %d batch(es); destroy them before changing its layout",
                         map->batch_refs);
     }
-    if (map->dm.layout == layout) return NBT_IG_OK;
-    DeviceGuard g(ctx->device);
-    if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", ctx->device);
-    DevMap nd = map->dm;
-    nd.layout = layout;
-    const uint64_t words = layout == NBT_IG_LAYOUT_BRICK4 ? (uint64_t)nd.nbx * nd.nby * nd.nbz * 64
-                                                          : (uint64_t)nd.px * nd.py * nd.pz;
-    if (words >= (1ull << 30)) return fail(NBT_IG_EUNSUPPORTED, "map too large for this layout");
-    uint32_t* enc = nullptr;
-    hipError_t e = hipMalloc(&enc, words * 4);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(map)");
-    nd.enc = enc;
-    nd.bytes = (uint32_t)(words * 4);
-    hipStream_t s = (hipStream_t)stream;
-    e = launch_relayout(map->dm, enc, nd, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);     // the old words are read until here
-    if (e != hipSuccess) {
-        (void)hipFree(enc);
-        return hip_fail(e, "relayout_kernel");
-    }
-    (void)hipFree(map->enc);
-    map->enc = enc;
-    map->enc_bytes = words * 4;
-    map->dm = nd;
-    return NBT_IG_OK;
+    return relayout_map(map, layout, (hipStream_t)stream);
 }
 
 int nbt_ig_map_layout(const nbt_ig_map* map, int* layout) {

@@ -148,6 +148,15 @@ def test_batch_launch_shapes_and_autotune(nbt, ctx, uneven):
         assert np.array_equal(st.cpu().numpy(), st_single), shape
     best, ms = b.autotune(off, dp, ig, st)
     assert ms > 0 and best["waves_per_group"] in (2, 4, 8)
+    lay, lms = b.autotune_layout(off, dp, ig, st)          # maps rewritten; results unchanged
+    assert lay in (0, 1) and lms > 0 and all(m.info()["layout"] == lay for m in maps)
+    b.run(off, dp, ig, st)
+    torch.cuda.synchronize()
+    assert np.array_equal(st.cpu().numpy(), st_single)
+    other = nbt.Batch(ctx, maps[:1], cam, 64)               # a map held twice cannot be rewritten
+    with pytest.raises(nbt.NbtError):
+        b.autotune_layout(off, dp, ig, st)
+    other.close()
     b.run(off, dp, ig, st)
     torch.cuda.synchronize()
     assert np.array_equal(st.cpu().numpy(), st_single)
