@@ -128,8 +128,8 @@ def extra_trajectories(nbt, ctx, reps):
     w = make_config(4)
     sc, cam, traj = w.maps[0], w.camera, w.poses[0]
     m = nbt.Map(ctx, sc.P, sc.voxel, sc.origin)
-    m.set_layout(nbt.LAYOUT_LINEAR)     # rays denser than the 5 cm voxels: the linear order is faster
     dt = torch.from_numpy(traj).cuda()
+    layout, waves, _ = nbt.autotune_trajectories(m, cam, dt)
     out = {}
 
     def run():
@@ -143,6 +143,7 @@ def extra_trajectories(nbt, ctx, reps):
             "ms_per_launch": ms, "trajectory_evals_per_s": traj.shape[0] / (ms * 1e-3),
             "rays_per_s": rays / (ms * 1e-3), "voxel_steps_per_s": vis / (ms * 1e-3),
             "mean_unique_voxels": float(counts[:, 0].float().mean().item()),
+            "map_layout": "brick4" if layout == nbt.LAYOUT_BRICK4 else "linear", "waves_per_group": waves,
             "note": "includes the box pre-pass and its one host synchronisation"}
 
 

@@ -302,6 +302,16 @@ int nbt_ig_batch_autotune_layout(nbt_ig_batch* batch, const uint32_t* vp_offsets
                                  float* ig_out, uint64_t* steps_out, void* stream, int* best_layout,
                                  float* best_ms);
 
+/* For trajectory IG: times nbt_ig_eval_trajectories on both storage orders of
+ * the map and each trajectory workgroup size (4, 8, 16 waves), keeps the
+ * fastest (the map rewritten in *best_layout, the context set to *best_waves;
+ * HOST outputs, mean ms per call in *best_ms).  Outputs are written as by the
+ * evaluation.  Synchronises `stream`; the map must not be held by a batch. */
+int nbt_ig_autotune_trajectories(nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                                 uint32_t n_traj, uint32_t poses_per_traj, float* ig_union, uint32_t* counts,
+                                 uint64_t* visits, void* stream, int* best_layout, int* best_waves,
+                                 float* best_ms);
+
 /* As nbt_ig_autotune_viewpoints, and first the map's storage order: times
  * nbt_ig_eval_viewpoints on both orders at the context's launch shape, keeps
  * the map in the faster one (*best_layout, HOST; see nbt_ig_map_set_layout),

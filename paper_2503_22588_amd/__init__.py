@@ -8,14 +8,14 @@ package fails when the library has not been built.
 from . import binding
 from .binding import (
     NbtError, Context, Map, Batch, Surrogate, CameraT, camera, camera_from_grid, autotune_viewpoints,
-    autotune_map, extract_patch, eval_cost, top_k,
+    autotune_map, autotune_trajectories, extract_patch, eval_cost, top_k,
     eval_viewpoints, eval_trajectories, trace_rays, trace_paths,
     RAY_MISS, RAY_HIT, RAY_END, RAY_EXIT, RAY_INVALID, LAYOUT_LINEAR, LAYOUT_BRICK4,
 )
 
 __all__ = [
     "binding", "NbtError", "Context", "Map", "Batch", "CameraT", "camera", "camera_from_grid",
-    "autotune_viewpoints", "autotune_map", "Surrogate", "extract_patch", "eval_cost", "top_k",
+    "autotune_viewpoints", "autotune_map", "autotune_trajectories", "Surrogate", "extract_patch", "eval_cost", "top_k",
     "eval_viewpoints", "eval_trajectories", "trace_rays", "trace_paths",
     "RAY_MISS", "RAY_HIT", "RAY_END", "RAY_EXIT", "RAY_INVALID", "LAYOUT_LINEAR", "LAYOUT_BRICK4",
 ]

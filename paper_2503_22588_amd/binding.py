@@ -101,6 +101,8 @@ _sig("nbt_ig_autotune_viewpoints", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, 
      C.POINTER(LaunchT), C.POINTER(C.c_float))
 _sig("nbt_ig_batch_autotune", C.c_int, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(LaunchT), C.POINTER(C.c_float))
 _sig("nbt_ig_batch_autotune_layout", C.c_int, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_int), C.POINTER(C.c_float))
+_sig("nbt_ig_autotune_trajectories", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _u32, _vp, _vp, _vp, _vp,
+     C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_float))
 _sig("nbt_ig_surrogate_create", C.c_int, _vp, C.c_void_p, C.c_size_t, C.POINTER(_vp))
 _sig("nbt_ig_surrogate_destroy", None, _vp)
 _sig("nbt_ig_surrogate_predict", C.c_int, _vp, _vp, C.POINTER(C.c_float), _vp, _u32, _vp, _vp)
@@ -473,6 +475,25 @@ def autotune_map(m: Map, cam, poses, ig_out=None, steps_out=None, stream=None):
                                     _dev_ptr(steps_out, torch.int64, "steps_out"), _stream(stream),
                                     C.byref(l), C.byref(lay), C.byref(ms)))
     return _launch_dict(l), lay.value, ms.value
+
+
+def autotune_trajectories(m: Map, cam, poses, stream=None):
+    """Pick the storage order of the map (it is rewritten in it) and the trajectory workgroup
+    size (the context keeps it) that run eval_trajectories fastest on these poses [T, L, 12].
+    Returns (layout, waves, ms)."""
+    torch = _torch()
+    T, L = int(poses.shape[0]), int(poses.shape[1])
+    dev = poses.device
+    ig = torch.empty(T, dtype=torch.float32, device=dev)
+    counts = torch.empty((T, 4), dtype=torch.int32, device=dev)
+    visits = torch.empty(T, dtype=torch.int64, device=dev)
+    cm = camera(cam)
+    lay, w, ms = C.c_int(), C.c_int(), C.c_float()
+    _check(_lib.nbt_ig_autotune_trajectories(m.handle, C.byref(cm), _dev_ptr(poses, torch.float32, "poses"), T, L,
+                                             _dev_ptr(ig, torch.float32, "ig"), _dev_ptr(counts, None, "counts"),
+                                             _dev_ptr(visits, None, "visits"), _stream(stream), C.byref(lay),
+                                             C.byref(w), C.byref(ms)))
+    return lay.value, w.value, ms.value
 
 
 def _poi(poi):

@@ -341,6 +341,58 @@ int nbt_ig_batch_autotune_layout(nbt_ig_batch* b, const uint32_t* vp_offsets, co
     return NBT_IG_OK;
 }
 
+int nbt_ig_autotune_trajectories(nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                                 uint32_t n_traj, uint32_t poses_per_traj, float* ig_union, uint32_t* counts,
+                                 uint64_t* visits, void* stream, int* best_layout, int* best_waves,
+                                 float* best_ms) {
+    if (int rc = check_map(map)) return rc;
+    if (!best_layout || !best_waves || !best_ms) return fail(NBT_IG_EINVAL, "an output is NULL");
+    if (n_traj == 0) return fail(NBT_IG_EINVAL, "autotuning needs trajectories");
+    nbt_ig_ctx* ctx = map->ctx;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(NBT_IG_EDEVICE, "hipEventCreate failed");
+    static const int waves[] = {4, 8, 16};
+    float best = 0.0f;
+    int bl = map->dm.layout, bw = ctx->traj_waves;
+    int rc = NBT_IG_OK;
+    const int start = map->dm.layout;
+    for (int i = 0; i < 2 && rc == NBT_IG_OK; ++i) {
+        const int lay = i == 0 ? start : 1 - start;
+        rc = nbt_ig_map_set_layout(map, lay, stream);
+        for (int w = 0; w < 3 && rc == NBT_IG_OK; ++w) {
+            rc = nbt_ig_ctx_set_traj_waves(ctx, waves[w]);
+            if (rc == NBT_IG_OK)
+                rc = nbt_ig_eval_trajectories(map, cam, poses, n_traj, poses_per_traj, ig_union, counts, visits,
+                                              stream);
+            hipError_t e = rc == NBT_IG_OK ? hipEventRecord(e0, s) : hipSuccess;
+            for (int r = 0; r < 2 && rc == NBT_IG_OK && e == hipSuccess; ++r)
+                rc = nbt_ig_eval_trajectories(map, cam, poses, n_traj, poses_per_traj, ig_union, counts, visits,
+                                              stream);
+            float ms = 0.0f;
+            if (rc == NBT_IG_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+            if (rc == NBT_IG_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+            if (rc == NBT_IG_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (rc == NBT_IG_OK && e != hipSuccess) rc = hip_fail(e, "trajectory timing");
+            if (rc == NBT_IG_OK && (best == 0.0f || ms < best)) {
+                best = ms;
+                bl = lay;
+                bw = waves[w];
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != NBT_IG_OK) return rc;
+    if (int r2 = nbt_ig_map_set_layout(map, bl, stream)) return r2;
+    if (int r2 = nbt_ig_ctx_set_traj_waves(ctx, bw)) return r2;
+    *best_layout = bl;
+    *best_waves = bw;
+    *best_ms = best / 2.0f;
+    return NBT_IG_OK;
+}
+
 int nbt_ig_autotune_map(nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses, uint32_t n,
                         float* ig_out, uint64_t* steps_out, void* stream, nbt_ig_launch* best,
                         int* best_layout, float* best_ms) {

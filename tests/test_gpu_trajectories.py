@@ -103,6 +103,22 @@ def test_small_global_and_mixed_paths(nbt, ctx, small):
         ctx.set_traj_waves(8)
 
 
+def test_autotune_trajectories(nbt, ctx, small):
+    sc, cam, traj, _, ref = small
+    _note("trajectories: autotuner")
+    m = nbt.Map(ctx, sc.P, sc.voxel, sc.origin)
+    try:
+        lay, waves, ms = nbt.autotune_trajectories(m, cam, _dev(traj))
+        assert lay in (nbt.LAYOUT_LINEAR, nbt.LAYOUT_BRICK4) and waves in (4, 8, 16) and ms > 0
+        assert m.info()["layout"] == lay and ctx.get_traj_waves() == waves
+        _check(_run(nbt, m, cam, traj), ref)
+        with pytest.raises(nbt.NbtError):
+            nbt.autotune_trajectories(m, cam, _dev(traj[:0]))
+    finally:
+        ctx.set_traj_waves(8)
+        m.close()
+
+
 def test_single_pose_equals_distinct_voxels(nbt, ctx, small):
     import torch
     sc, cam, traj, m, _ = small
