@@ -263,12 +263,16 @@ __device__ __forceinline__ void dda_advance(float& tx, float& ty, float& tz, uin
 // flight per lane; the consumer adds gains in visiting order and stops at
 // the first Occupied word or at a sentinel (the border, or the corner word
 // the generator reads once the segment has ended).  Visits, gains and their
-// order are exactly those of walk_ray; only the reason is not reported, and
-// the visit count only when COUNT is set.  Gathers past a stop are never
+// order are exactly those of walk_ray (the sum is rounded differently, see
+// below); only the reason is not reported, and the visit count only when
+// COUNT is set.  Gathers past a stop are never
 // consumed (and out-of-range ones read 0).  BRICK selects the map layout.
+constexpr uint32_t kRunSlots = 8;
+
 template <int P, bool COUNT, bool BRICK>
 __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buffer_rsrc_t rs,
                                                    const RayState& r, double& acc, uint32_t& steps) {
+    static_assert(P == 2 || P == 4 || P == 8, "pipeline depth");
     const OffsetSteps o = offset_steps<BRICK>(m, r);
     const float dtx = r.dtx, dty = r.dty, dtz = r.dtz;
     const float t1 = r.t1;
@@ -289,6 +293,12 @@ __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buf
     // nx + ny + nz steps; the group budget only guards that argument.
     uint32_t budget = (uint32_t)(m.nx + m.ny + m.nz + 3) / P + 2;
     bool run = true;
+    // Gains are summed in binary32 over runs of kRunSlots consecutive slots and
+    // each run's sum is added to the double accumulator.  The runs start at
+    // fixed slot indices whatever P is, so every depth gives the same bits; a
+    // sum of 8 non-negative terms is off by at most 7 units of 2^-24 relative.
+    float part = 0.0f;
+    uint32_t group = 0;
     // Lanes leave the loop between groups of P slots; inside a group every slot
     // runs for every lane still in the loop, with a lane that has stopped adding
     // nothing.  No slot is conditional, so slot u's word lives in one register
@@ -300,18 +310,24 @@ __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buf
         for (int u = 0; u < P; ++u) {
             const uint32_t x = w[u];
             const bool take = run && x < kMarkerMin;
-            // select the word before widening it (one 32-bit select instead of two)
+            // the empty asm keeps each slot's read ahead of its refill (else the
+            // reads sink to the end of the group and the refills need copies)
             uint32_t xs = take ? x : 0u;
             asm volatile("" : "+v"(xs));
-            acc += (double)fabsf(__uint_as_float(xs));
+            part += fabsf(__uint_as_float(xs));
             if constexpr (COUNT) n += take ? 1u : 0u;
             run = run && (int)x >= 0;
             dda_advance<BRICK>(tx, ty, tz, off, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.bigz, o.flip,
                                dtx, dty, dtz);
             w[u] = load_word(rs, off);
         }
+        if ((++group & (kRunSlots / P - 1)) == 0u) {
+            acc += (double)part;
+            part = 0.0f;
+        }
         run = run && --budget != 0u;
     }
+    acc += (double)part;
     if constexpr (COUNT) steps += n;
 }
 
