@@ -22,6 +22,108 @@
 
 namespace nbt {
 
+// dda_advance plus a second index (a bitset position) that moves with the
+// map offset: by dbx/dby/dbz per step on x/y/z.  Past the segment end it
+// drifts, but every slot from there on reads the sentinel and is never
+// marked, so it needs no gating.
+template <bool BRICK>
+__device__ __forceinline__ void dda_advance_idx(float& tx, float& ty, float& tz, uint32_t& off,
+                                                int& idx, bool& alive, float t1, int dxo, int dyo, int dzo,
+                                                int bxo, int byo, int bzo, uint32_t flip, int dbx, int dby,
+                                                int dbz, float dtx, float dty, float dtz) {
+    const float x = tx, y = ty, z = tz;
+    const float tm = fminf(fminf(x, y), z);
+    const bool go = alive && !(tm > t1);
+    const bool ex = x == tm, ey = y == tm;
+    const bool bx = go && ex;
+    const bool by = go && !ex && ey;
+    const bool bz = go && !ex && !ey;
+    int d = bx ? dxo : (by ? dyo : dzo);
+    if constexpr (BRICK) {
+        const uint32_t msk = bx ? 0x0Cu : (by ? 0x30u : 0xC0u);
+        const int big = bx ? bxo : (by ? byo : bzo);
+        d = ((off ^ flip) & msk) == 0u ? big : d;
+    }
+    off = go ? off + (uint32_t)d : 0u;
+    idx += bx ? dbx : (by ? dby : dbz);
+    const float nt = tm + (bx ? dtx : (by ? dty : dtz));
+    tx = bx ? nt : x;
+    ty = by ? nt : y;
+    tz = bz ? nt : z;
+    alive = go;
+}
+
+// Pipelined walk that also sets, in `bits`, the bit of every visited voxel of
+// the box [lo, lo + (ax, ay, *)): ((z-lz)*ay + (y-ly))*ax + (x-lx).  Indices
+// at or beyond nbits (a voxel outside the box, impossible when the box
+// contains the ray's frustum) are skipped.  Along a trajectory almost every
+// visit finds its bit already set, so a slot reads the word and only an unset
+// bit costs an atomic OR; the read of slot u is checked one slot later, which
+// keeps its latency off the walk.  Setting a bit twice is harmless, and a
+// stale read can only show fewer bits than are set, so the set of marked
+// voxels is exactly the set visited.  CHECK = false sets every visit with an
+// atomic OR (for bitsets in global memory, where a read could be served by a
+// stale L1 line).  Returns the number of voxels visited.
+template <int P, bool CHECK, bool BRICK>
+__device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buffer_rsrc_t rs,
+                                                  const RayState& r, int lx, int ly, int lz, int ax,
+                                                  int ay, uint32_t nbits, uint32_t* bits) {
+    const OffsetSteps o = offset_steps<BRICK>(m, r);
+    const int dbx = r.sx, dby = r.sy * ax, dbz = r.sz * ax * ay;
+    const float dtx = r.dtx, dty = r.dty, dtz = r.dtz;
+    const float t1 = r.t1;
+    uint32_t off = voxel_offset(m, r.ix, r.iy, r.iz);
+    int bidx = ((r.iz - lz) * ay + (r.iy - ly)) * ax + (r.ix - lx);
+    float tx = r.tx, ty = r.ty, tz = r.tz;
+    const uint32_t guard = (uint32_t)(m.nx + m.ny + m.nz + 3);
+    bool alive = true;
+
+    uint32_t w[P];
+    int bi[P];
+    w[0] = load_word(rs, off);
+    bi[0] = bidx;
+#pragma unroll
+    for (int u = 1; u < P; ++u) {
+        dda_advance_idx<BRICK>(tx, ty, tz, off, bidx, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.bigz, o.flip,
+                               dbx, dby, dbz, dtx, dty, dtz);
+        w[u] = load_word(rs, off);
+        bi[u] = bidx;
+    }
+    uint32_t n = 0;
+    bool run = true;
+    uint32_t pend_word = 0, pend_mask = 0, pend_seen = 0;    // the previous slot's mark
+    // Same slot structure as walk_ray_pipelined.
+    while (run) {
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            const uint32_t x = w[u];
+            const bool take = run && x < kMarkerMin;
+            const bool mark = take && (uint32_t)bi[u] < nbits;
+            if constexpr (CHECK) {
+                if (pend_mask & ~pend_seen) atomicOr(&bits[pend_word], pend_mask);
+                pend_word = mark ? (uint32_t)bi[u] >> 5 : 0u;
+                pend_mask = mark ? 1u << ((uint32_t)bi[u] & 31u) : 0u;
+                pend_seen = bits[pend_word];
+                // keep this slot's generator step after the read, so that the
+                // read has the step's latency to complete before it is checked
+                __builtin_amdgcn_sched_barrier(0);
+            } else if (mark) {
+                atomicOr(&bits[(uint32_t)bi[u] >> 5], 1u << ((uint32_t)bi[u] & 31u));
+            }
+            n += take ? 1u : 0u;
+            run = run && (int)x >= 0;
+            dda_advance_idx<BRICK>(tx, ty, tz, off, bidx, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.bigz, o.flip,
+                               dbx, dby, dbz, dtx, dty, dtz);
+            w[u] = load_word(rs, off);
+            bi[u] = bidx;
+        }
+        run = run && n < guard;      // the border bounds n below nx + ny + nz; guard only
+    }
+    if constexpr (CHECK)
+        if (pend_mask & ~pend_seen) atomicOr(&bits[pend_word], pend_mask);
+    return n;
+}
+
 __global__ __launch_bounds__(256) void traj_box_kernel(DevMap m, CamParams c,
                                                        const float* __restrict__ poses, uint32_t T,
                                                        uint32_t L, uint32_t budget_bits,
