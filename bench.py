@@ -294,6 +294,8 @@ def main():
                     help="map storage order (default: the library's)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the trajectory and batched measurements")
+    ap.add_argument("--only", choices=("trajectories", "batched", "surrogate"), default=None,
+                    help="only run one of the extra workloads (one JSON object)")
     ap.add_argument("--e1-sweep", action="store_true",
                     help="only run the N_P x s_G runtime sweep at 1 cm voxels (one JSON object per line)")
     ap.add_argument("--fingerprint", action="store_true",
@@ -331,6 +333,13 @@ def main():
 
     if args.e1_sweep:
         e1_sweep(nbt, nbt.Context(0))
+        return
+    if args.only:
+        cx = nbt.Context(0)
+        run = {"trajectories": lambda: extra_trajectories(nbt, cx, reps=3),
+               "batched": lambda: extra_batch(nbt, cx, reps=5),
+               "surrogate": lambda: extra_surrogate(nbt, cx)}[args.only]
+        print(json.dumps({args.only: run()}), flush=True)
         return
 
     t_gen = time.perf_counter()
@@ -448,7 +457,7 @@ def main():
         result["roofline"]["traffic"] = traffic_b / (ray_ms * 1e-3) / 1e9
         result["roofline"]["traffic_gb_per_launch"] = traffic_b / 1e9
         result["binding_unit"] = {
-            "unit": "TA (vector-memory address path)",
+            "unit": "TA (vector-memory address path) and VALU issue",
             "ta_busy_frac": float(counters["TA busy fraction"]),
             "valu_instr_per_cu_cycle": float(counters["VALU per CU-cycle"]),
             "tcp_accesses_per_gather": float(counters["L1 accesses per gather"]),
