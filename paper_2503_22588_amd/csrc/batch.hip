@@ -123,8 +123,11 @@ int launch_search(VpLaunch start, hipStream_t s, int reps, Apply&& apply, Run&& 
     static const int tpws[] = {0, 4, 16};          // 0: balanced for the camera
     static const int depths[] = {2, 4, 8};
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    if (hipEventCreate(&e0) != hipSuccess) return fail(NBT_IG_EDEVICE, "hipEventCreate failed");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
         return fail(NBT_IG_EDEVICE, "hipEventCreate failed");
+    }
     auto time = [&](const VpLaunch& L, float* ms) -> int {
         if (int rc = apply(L)) return rc;
         if (int rc = run()) return rc;                 // warm-up (and graph build)
@@ -311,8 +314,11 @@ int nbt_ig_batch_autotune_layout(nbt_ig_batch* b, const uint32_t* vp_offsets, co
     const int start = b->maps.empty() ? NBT_IG_LAYOUT_LINEAR : b->maps[0]->dm.layout;
     float ms[2] = {0.0f, 0.0f};
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    if (hipEventCreate(&e0) != hipSuccess) return fail(NBT_IG_EDEVICE, "hipEventCreate failed");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
         return fail(NBT_IG_EDEVICE, "hipEventCreate failed");
+    }
     int rc = NBT_IG_OK;
     for (int i = 0; i < 2 && rc == NBT_IG_OK; ++i) {
         const int lay = i == 0 ? start : 1 - start;
@@ -346,11 +352,16 @@ int nbt_ig_autotune_trajectories(nbt_ig_map* map, const nbt_ig_camera* cam, cons
     nbt_ig_ctx* ctx = map->ctx;
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    if (hipEventCreate(&e0) != hipSuccess) return fail(NBT_IG_EDEVICE, "hipEventCreate failed");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
         return fail(NBT_IG_EDEVICE, "hipEventCreate failed");
+    }
     static const int waves[] = {4, 8, 16};
     float best = 0.0f;
-    int bl = map->dm.layout, bw = ctx->traj_waves;
+    bool have = false;
+    const int orig_waves = ctx->traj_waves;
+    int bl = map->dm.layout, bw = orig_waves;
     int rc = NBT_IG_OK;
     const int start = map->dm.layout;
     for (int i = 0; i < 2 && rc == NBT_IG_OK; ++i) {
@@ -370,7 +381,8 @@ int nbt_ig_autotune_trajectories(nbt_ig_map* map, const nbt_ig_camera* cam, cons
             if (rc == NBT_IG_OK && e == hipSuccess) e = hipEventSynchronize(e1);
             if (rc == NBT_IG_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             if (rc == NBT_IG_OK && e != hipSuccess) rc = hip_fail(e, "trajectory timing");
-            if (rc == NBT_IG_OK && (best == 0.0f || ms < best)) {
+            if (rc == NBT_IG_OK && (!have || ms < best)) {
+                have = true;
                 best = ms;
                 bl = lay;
                 bw = waves[w];
@@ -379,7 +391,11 @@ int nbt_ig_autotune_trajectories(nbt_ig_map* map, const nbt_ig_camera* cam, cons
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (rc != NBT_IG_OK) return rc;
+    if (rc != NBT_IG_OK) {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->traj_waves = orig_waves;      // the map keeps whichever order it reached
+        return rc;
+    }
     if (int r2 = nbt_ig_map_set_layout(map, bl, stream)) return r2;
     if (int r2 = nbt_ig_ctx_set_traj_waves(ctx, bw)) return r2;
     *best_layout = bl;
@@ -399,8 +415,11 @@ int nbt_ig_autotune_map(nbt_ig_map* map, const nbt_ig_camera* cam, const float* 
     const int start = map->dm.layout;
     float ms[2] = {0.0f, 0.0f};
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    if (hipEventCreate(&e0) != hipSuccess) return fail(NBT_IG_EDEVICE, "hipEventCreate failed");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
         return fail(NBT_IG_EDEVICE, "hipEventCreate failed");
+    }
     int rc = NBT_IG_OK;
     for (int i = 0; i < 2 && rc == NBT_IG_OK; ++i) {
         const int lay = i == 0 ? start : 1 - start;
