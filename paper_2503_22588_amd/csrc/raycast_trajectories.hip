@@ -46,10 +46,11 @@ __device__ __forceinline__ void dda_advance_idx(float& tx, float& ty, float& tz,
     }
     off = go ? off + (uint32_t)d : 0u;
     idx += bx ? dbx : (by ? dby : dbz);
-    const float nt = tm + (bx ? dtx : (by ? dty : dtz));
-    tx = bx ? nt : x;
-    ty = by ? nt : y;
-    tz = bz ? nt : z;
+    // the stepping axis gains its delta, the others add +0 (t >= 0, so exact):
+    // three selects and three adds instead of five selects and one add
+    tx = x + (bx ? dtx : 0.0f);
+    ty = y + (by ? dty : 0.0f);
+    tz = z + (bz ? dtz : 0.0f);
     alive = go;
 }
 
