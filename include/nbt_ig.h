@@ -79,7 +79,8 @@ enum { NBT_IG_OCCUPIED = 1, NBT_IG_FREE = 2, NBT_IG_UNKNOWN = 3 };
 /* Device storage order of an encoded map (nbt_ig_ctx_set_map_layout). */
 enum {
     NBT_IG_LAYOUT_LINEAR = 0,   /* x fastest over the bordered grid */
-    NBT_IG_LAYOUT_BRICK4 = 1    /* 4x4x4 bricks of 256 B (x fastest inside), bricks x fastest */
+    NBT_IG_LAYOUT_COLUMN4 = 1   /* 4x4 columns: the x-y plane in 4x4 tiles (64 B, x fastest), a tile's
+                                   layers stored z after z, tiles x fastest */
 };
 
 typedef struct nbt_ig_ctx nbt_ig_ctx;
@@ -120,7 +121,7 @@ void nbt_ig_ctx_destroy(nbt_ig_ctx* ctx);       /* NULL is a no-op; caller syncs
                                                    the context's batches, surrogates and maps first */
 
 /* Storage order of the maps this context creates from now on
- * (NBT_IG_LAYOUT_*, default NBT_IG_LAYOUT_BRICK4; NBT_IG_EINVAL otherwise).  Every call gives the same
+ * (NBT_IG_LAYOUT_*, default NBT_IG_LAYOUT_COLUMN4; NBT_IG_EINVAL otherwise).  Every call gives the same
  * results on either; the order only changes how many cache lines one
  * 64-ray gather touches.  The getter reports the current setting;
  * nbt_ig_map_layout the order of an existing map. */
@@ -133,7 +134,7 @@ int nbt_ig_ctx_get_map_layout(const nbt_ig_ctx* ctx, int* layout);
  * voxel stores its Eq. 2 gain with the sign bit marking Occupied, inside a
  * one-voxel border that stops every ray leaving the map, stored in the
  * context's map layout.  1 <= n <= 4096 per axis and (nx+2)(ny+2)(nz+2) <
- * 2^30 (for 4x4x4 bricks: the brick-padded count < 2^30).  `origin` (HOST, 3 floats) is the world
+ * 2^30 (for 4x4 columns: the count with x and y padded to multiples of 4 < 2^30).  `origin` (HOST, 3 floats) is the world
  * position of the min corner of voxel (0,0,0); `voxel_size` > 0 is s_Vox.
  * `cls` may be NULL (0.5/0.5); 0 <= free_threshold <= occ_threshold <= 1.
  * Probabilities outside [0,1] or NaN give NBT_IG_EINVAL (checked on the

@@ -335,7 +335,7 @@ int nbt_ig_batch_autotune_layout(nbt_ig_batch* b, const uint32_t* vp_offsets, co
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != NBT_IG_OK) return rc;
-    const int lay = ms[NBT_IG_LAYOUT_BRICK4] < ms[NBT_IG_LAYOUT_LINEAR] ? NBT_IG_LAYOUT_BRICK4 : NBT_IG_LAYOUT_LINEAR;
+    const int lay = ms[NBT_IG_LAYOUT_COLUMN4] < ms[NBT_IG_LAYOUT_LINEAR] ? NBT_IG_LAYOUT_COLUMN4 : NBT_IG_LAYOUT_LINEAR;
     if (int r2 = apply(lay)) return r2;
     *best_layout = lay;
     *best_ms = ms[lay] / 3.0f;
@@ -436,7 +436,7 @@ int nbt_ig_autotune_map(nbt_ig_map* map, const nbt_ig_camera* cam, const float* 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != NBT_IG_OK) return rc;
-    const int lay = ms[NBT_IG_LAYOUT_BRICK4] < ms[NBT_IG_LAYOUT_LINEAR] ? NBT_IG_LAYOUT_BRICK4 : NBT_IG_LAYOUT_LINEAR;
+    const int lay = ms[NBT_IG_LAYOUT_COLUMN4] < ms[NBT_IG_LAYOUT_LINEAR] ? NBT_IG_LAYOUT_COLUMN4 : NBT_IG_LAYOUT_LINEAR;
     if (int r2 = nbt_ig_map_set_layout(map, lay, stream)) return r2;
     *best_layout = lay;
     return nbt_ig_autotune_viewpoints(map, cam, poses, n, ig_out, steps_out, stream, best, best_ms);

@@ -53,7 +53,7 @@ struct nbt_ig_ctx {
     size_t lds_max = 0;             // device limit of LDS per workgroup (bytes)
     size_t lds_budget = 0;          // LDS a trajectory bitset may use (bytes)
     int traj_waves = 8;             // wavefronts per trajectory workgroup (4, 8, 16)
-    int map_layout = NBT_IG_LAYOUT_BRICK4;   // storage order of maps created next
+    int map_layout = NBT_IG_LAYOUT_COLUMN4;  // storage order of maps created next
     // trajectory workspace
     nbt::TrajBox* boxes = nullptr;
     uint32_t* over_list = nullptr;

@@ -22,12 +22,15 @@ constexpr uint32_t kGainOne = 0x3F800000u;   // 1.0f: the gain of an Unknown vox
 // Storage order of the encoded words over the padded grid (X, Y, Z) =
 // (x+1, y+1, z+1):
 //   kLayoutLinear  x fastest: (Z*py + Y)*px + X;
-//   kLayoutBrick4  4x4x4 bricks of 64 words (256 B = two 128-B lines), x fastest
-//                  inside a brick and bricks x fastest over the brick grid:
-//                  ((Z/4*nby + Y/4)*nbx + X/4)*64 + (Z%4)*16 + (Y%4)*4 + X%4.
-// Padding up to whole bricks holds the sentinel as well.
+//   kLayoutColumn4 4x4 columns: the x-y plane is cut into 4x4 tiles of 16
+//                  words (64 B, x fastest), each tile stores its layers z
+//                  after z, and tiles go x fastest over the tile grid:
+//                  ((Y/4*nbx + X/4)*pz + Z)*16 + (Y%4)*4 + X%4.
+//                  A 128-B line holds a 4x4x2 block and four aligned layers
+//                  a contiguous 4x4x4 block (256 B); a z step is always +-64 B.
+// Padding of x and y up to whole tiles holds the sentinel as well.
 constexpr int kLayoutLinear = NBT_IG_LAYOUT_LINEAR;
-constexpr int kLayoutBrick4 = NBT_IG_LAYOUT_BRICK4;
+constexpr int kLayoutColumn4 = NBT_IG_LAYOUT_COLUMN4;
 
 // Device view of an encoded map (passed to kernels by value).
 struct DevMap {
@@ -35,8 +38,8 @@ struct DevMap {
     uint32_t bytes;         // size of enc in bytes (< 2^32)
     int nx, ny, nz;         // real dimensions
     int px, py, pz;         // padded dimensions (n + 2)
-    int layout;             // kLayoutLinear or kLayoutBrick4
-    int nbx, nby, nbz;      // bricks per axis over the padded grid (kLayoutBrick4)
+    int layout;             // kLayoutLinear or kLayoutColumn4
+    int nbx, nby;           // tiles per axis over the padded x-y plane (kLayoutColumn4)
     float inv_s;            // 1/voxel_size (binary32)
     float ox, oy, oz;       // origin
 };
@@ -46,8 +49,8 @@ struct DevMap {
 __host__ __device__ inline uint32_t voxel_offset(const DevMap& m, int x, int y, int z) {
     const uint32_t X = (uint32_t)(x + 1), Y = (uint32_t)(y + 1), Z = (uint32_t)(z + 1);
     if (m.layout == kLayoutLinear) return ((Z * (uint32_t)m.py + Y) * (uint32_t)m.px + X) * 4u;
-    const uint32_t brick = ((Z >> 2) * (uint32_t)m.nby + (Y >> 2)) * (uint32_t)m.nbx + (X >> 2);
-    return (brick * 64u + ((Z & 3u) << 4 | (Y & 3u) << 2 | (X & 3u))) * 4u;
+    const uint32_t tile = (Y >> 2) * (uint32_t)m.nbx + (X >> 2);
+    return ((tile * (uint32_t)m.pz + Z) * 16u + ((Y & 3u) << 2 | (X & 3u))) * 4u;
 }
 
 // Endpoint-grid parameters derived once per launch on the host.

@@ -3,7 +3,7 @@
 // Each voxel is classified once (Occupied if P > occ, Free if P < free,
 // Unknown otherwise) and stored as its Eq. 2 gain (1-P, P or 1) in float32
 // bits, with the sign bit set for Occupied.  A one-voxel border of sentinel
-// words surrounds the map (and fills the padding of the brick layout).  The
+// words surrounds the map (and fills the tile padding of the column layout).  The
 // walk then needs one 4-byte gather and one signed compare per voxel: no
 // probability, no threshold and no bounds test is evaluated per step.
 // Streaming kernel, about 8 B per voxel.
@@ -11,7 +11,7 @@
 
 namespace nbt {
 
-// Word of padded voxel (X, Y, Z) (border and brick padding: the sentinel).
+// Word of padded voxel (X, Y, Z) (border and tile padding: the sentinel).
 __device__ __forceinline__ uint32_t encode_word(const float* __restrict__ prob, const DevMap& m, uint32_t X,
                                                 uint32_t Y, uint32_t Z, float occ_thr, float free_thr,
                                                 bool& any_bad) {
@@ -36,12 +36,11 @@ __device__ __forceinline__ void word_coords(const DevMap& m, uint32_t idx, uint3
         Y = yz % (uint32_t)m.py;
         Z = yz / (uint32_t)m.py;
     } else {
-        const uint32_t b = idx >> 6, l = idx & 63u;
-        const uint32_t bx = b % (uint32_t)m.nbx, byz = b / (uint32_t)m.nbx;
-        const uint32_t by = byz % (uint32_t)m.nby, bz = byz / (uint32_t)m.nby;
-        X = bx * 4 + (l & 3u);
-        Y = by * 4 + ((l >> 2) & 3u);
-        Z = bz * 4 + (l >> 4);
+        const uint32_t r = idx >> 4, l = idx & 15u;
+        Z = r % (uint32_t)m.pz;
+        const uint32_t tile = r / (uint32_t)m.pz;
+        X = (tile % (uint32_t)m.nbx) * 4 + (l & 3u);
+        Y = (tile / (uint32_t)m.nbx) * 4 + (l >> 2);
     }
 }
 
@@ -62,7 +61,7 @@ __global__ __launch_bounds__(256) void encode_map_kernel(const float* __restrict
 }
 
 // One thread per destination word: the word of the same padded voxel in the
-// source order (the sentinel for the padding of whole bricks).
+// source order (the sentinel for the padding of whole tiles).
 __global__ __launch_bounds__(256) void relayout_kernel(const uint32_t* __restrict__ src, DevMap sm,
                                                        uint32_t* __restrict__ dst, DevMap dm) {
     const uint32_t total = dm.bytes / 4u;

@@ -131,8 +131,8 @@ int relayout_map(nbt_ig_map* map, int layout, hipStream_t s) {
     if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", map->ctx->device);
     DevMap nd = map->dm;
     nd.layout = layout;
-    const uint64_t words = layout == NBT_IG_LAYOUT_BRICK4 ? (uint64_t)nd.nbx * nd.nby * nd.nbz * 64
-                                                          : (uint64_t)nd.px * nd.py * nd.pz;
+    const uint64_t words = layout == NBT_IG_LAYOUT_COLUMN4 ? (uint64_t)nd.nbx * nd.nby * 16 * nd.pz
+                                                           : (uint64_t)nd.px * nd.py * nd.pz;
     if (words >= (1ull << 30)) return fail(NBT_IG_EUNSUPPORTED, "map too large for this layout");
     uint32_t* enc = nullptr;
     hipError_t e = hipMalloc(&enc, words * 4);
@@ -223,9 +223,9 @@ int nbt_ig_create_map(nbt_ig_ctx* ctx, const float* prob, int nx, int ny, int nz
     if (nx < 1 || ny < 1 || nz < 1 || nx > 4096 || ny > 4096 || nz > 4096)
         return fail(NBT_IG_EINVAL, "map dims %dx%dx%d outside [1, 4096]", nx, ny, nz);
     const int layout = ctx->map_layout;
-    const int nbx = (nx + 2 + 3) / 4, nby = (ny + 2 + 3) / 4, nbz = (nz + 2 + 3) / 4;
-    const uint64_t padded = layout == NBT_IG_LAYOUT_BRICK4 ? (uint64_t)nbx * nby * nbz * 64
-                                                           : (uint64_t)(nx + 2) * (ny + 2) * (nz + 2);
+    const int nbx = (nx + 2 + 3) / 4, nby = (ny + 2 + 3) / 4;
+    const uint64_t padded = layout == NBT_IG_LAYOUT_COLUMN4 ? (uint64_t)nbx * nby * 16 * (uint64_t)(nz + 2)
+                                                            : (uint64_t)(nx + 2) * (ny + 2) * (nz + 2);
     if (padded >= (1ull << 30))
         return fail(NBT_IG_EUNSUPPORTED, "map %dx%dx%d: padded size must stay below 2^30 voxels", nx, ny, nz);
     if (!finite_pos(voxel_size)) return fail(NBT_IG_EINVAL, "voxel_size must be finite and > 0");
@@ -257,7 +257,7 @@ int nbt_ig_create_map(nbt_ig_ctx* ctx, const float* prob, int nx, int ny, int nz
     dm.nx = nx; dm.ny = ny; dm.nz = nz;
     dm.px = nx + 2; dm.py = ny + 2; dm.pz = nz + 2;
     dm.layout = layout;
-    dm.nbx = nbx; dm.nby = nby; dm.nbz = nbz;
+    dm.nbx = nbx; dm.nby = nby;
     dm.inv_s = 1.0f / voxel_size;
     dm.ox = origin[0]; dm.oy = origin[1]; dm.oz = origin[2];
 
@@ -429,7 +429,7 @@ int nbt_ig_ctx_set_lds_budget(nbt_ig_ctx* ctx, size_t bytes) {
 
 int nbt_ig_ctx_set_map_layout(nbt_ig_ctx* ctx, int layout) {
     if (!ctx) return fail(NBT_IG_EINVAL, "ctx is NULL");
-    if (layout != NBT_IG_LAYOUT_LINEAR && layout != NBT_IG_LAYOUT_BRICK4)
+    if (layout != NBT_IG_LAYOUT_LINEAR && layout != NBT_IG_LAYOUT_COLUMN4)
         return fail(NBT_IG_EINVAL, "unknown map layout %d", layout);
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->map_layout = layout;
@@ -444,7 +444,7 @@ int nbt_ig_ctx_get_map_layout(const nbt_ig_ctx* ctx, int* layout) {
 
 int nbt_ig_map_set_layout(nbt_ig_map* map, int layout, void* stream) {
     if (int rc = check_map(map)) return rc;
-    if (layout != NBT_IG_LAYOUT_LINEAR && layout != NBT_IG_LAYOUT_BRICK4)
+    if (layout != NBT_IG_LAYOUT_LINEAR && layout != NBT_IG_LAYOUT_COLUMN4)
         return fail(NBT_IG_EINVAL, "unknown map layout %d", layout);
     {
         std::lock_guard<std::mutex> lk(map->ctx->mu);

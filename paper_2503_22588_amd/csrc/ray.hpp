@@ -191,35 +191,36 @@ __device__ __forceinline__ int walk_ray(const DevMap& m, __amdgpu_buffer_rsrc_t 
 constexpr uint32_t kMarkerMin = 0xBF800001u;
 
 // Per-ray constants of the incremental map offset.  Linear layout: a step on
-// axis a adds d[a] bytes.  Brick layout: a step inside the brick adds d[a]
-// (the in-brick stride), a step across a brick face adds big[a]; the step
-// crosses when the voxel's in-brick coordinate on that axis is 3 (forward)
-// or 0 (backward), i.e. when ((off ^ flip) & mask_a) == 0, with the in-brick
-// x, y, z coordinates in bits 2-3, 4-5, 6-7 of the byte offset and flip
-// holding 3 in the fields of the forward axes.
+// axis a adds d[a] bytes.  Column layout: a z step adds dz (one 64-B layer);
+// an x or y step inside the 4x4 tile adds dx or dy (the in-tile stride) and
+// one across a tile face adds bigx or bigy.  The step crosses when the
+// voxel's in-tile coordinate on that axis is 3 (forward) or 0 (backward),
+// i.e. when ((off ^ flip) & mask) == 0, with the in-tile x and y in bits 2-3
+// and 4-5 of the byte offset and flip holding 3 in the fields of the forward
+// axes.
 struct OffsetSteps {
     int dx, dy, dz;
-    int bigx, bigy, bigz;
+    int bigx, bigy;
     uint32_t flip;
 };
 
-template <bool BRICK>
+template <bool COLUMN>
 __device__ __forceinline__ OffsetSteps offset_steps(const DevMap& m, const RayState& r) {
     OffsetSteps o;
-    if constexpr (!BRICK) {
+    if constexpr (!COLUMN) {
         o.dx = r.sx * 4;
         o.dy = r.sy * m.px * 4;
         o.dz = r.sz * m.px * m.py * 4;
-        o.bigx = o.bigy = o.bigz = 0;
+        o.bigx = o.bigy = 0;
         o.flip = 0;
     } else {
+        const int column = 64 * m.pz;          // bytes of one tile's column
         o.dx = r.sx * 4;
         o.dy = r.sy * 16;
         o.dz = r.sz * 64;
-        o.bigx = r.sx * (256 - 12);
-        o.bigy = r.sy * (256 * m.nbx - 48);
-        o.bigz = r.sz * (256 * m.nbx * m.nby - 192);
-        o.flip = (r.sx > 0 ? 0x0Cu : 0u) | (r.sy > 0 ? 0x30u : 0u) | (r.sz > 0 ? 0xC0u : 0u);
+        o.bigx = r.sx * (column - 12);
+        o.bigy = r.sy * (column * m.nbx - 48);
+        o.flip = (r.sx > 0 ? 0x0Cu : 0u) | (r.sy > 0 ? 0x30u : 0u);
     }
     return o;
 }
@@ -231,10 +232,10 @@ __device__ __forceinline__ OffsetSteps offset_steps(const DevMap& m, const RaySt
 // loaded value ever being inspected here (which would force a wait for it).
 // Loop invariants are passed by value so that the axis choice stays a
 // register select.
-template <bool BRICK>
+template <bool COLUMN>
 __device__ __forceinline__ void dda_advance(float& tx, float& ty, float& tz, uint32_t& off,
                                             bool& alive, float t1, int dxo, int dyo, int dzo,
-                                            int bxo, int byo, int bzo, uint32_t flip,
+                                            int bxo, int byo, uint32_t flip,
                                             float dtx, float dty, float dtz) {
     const float x = tx, y = ty, z = tz;
     const float tm = fminf(fminf(x, y), z);
@@ -243,11 +244,17 @@ __device__ __forceinline__ void dda_advance(float& tx, float& ty, float& tz, uin
     const bool bx = go && ex;
     const bool by = go && !ex && ey;
     const bool bz = go && !ex && !ey;
-    int d = bx ? dxo : (by ? dyo : dzo);
-    if constexpr (BRICK) {
-        const uint32_t msk = bx ? 0x0Cu : (by ? 0x30u : 0xC0u);
-        const int big = bx ? bxo : (by ? byo : bzo);
-        d = ((off ^ flip) & msk) == 0u ? big : d;
+    int d;
+    if constexpr (COLUMN) {
+        // x or y: the in-tile stride, or the tile-crossing delta at the tile
+        // face; z: one layer.  Two selects fewer than a 3-axis edge test.
+        const uint32_t msk = bx ? 0x0Cu : 0x30u;
+        const int big = bx ? bxo : byo;
+        const int small = bx ? dxo : dyo;
+        const int dxy = ((off ^ flip) & msk) == 0u ? big : small;
+        d = bz ? dzo : dxy;
+    } else {
+        d = bx ? dxo : (by ? dyo : dzo);
     }
     off = go ? off + (uint32_t)d : 0u;
     // the stepping axis gains its delta, the others add +0 (t >= 0, so exact):
@@ -267,14 +274,14 @@ __device__ __forceinline__ void dda_advance(float& tx, float& ty, float& tz, uin
 // order are exactly those of walk_ray (the sum is rounded differently, see
 // below); only the reason is not reported, and the visit count only when
 // COUNT is set.  Gathers past a stop are never
-// consumed (and out-of-range ones read 0).  BRICK selects the map layout.
+// consumed (and out-of-range ones read 0).  COLUMN selects the map layout.
 constexpr uint32_t kRunSlots = 8;
 
-template <int P, bool COUNT, bool BRICK>
+template <int P, bool COUNT, bool COLUMN>
 __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buffer_rsrc_t rs,
                                                    const RayState& r, double& acc, uint32_t& steps) {
     static_assert(P == 2 || P == 4 || P == 8, "pipeline depth");
-    const OffsetSteps o = offset_steps<BRICK>(m, r);
+    const OffsetSteps o = offset_steps<COLUMN>(m, r);
     const float dtx = r.dtx, dty = r.dty, dtz = r.dtz;
     const float t1 = r.t1;
     uint32_t off = voxel_offset(m, r.ix, r.iy, r.iz);
@@ -285,7 +292,7 @@ __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buf
     w[0] = load_word(rs, off);
 #pragma unroll
     for (int u = 1; u < P; ++u) {
-        dda_advance<BRICK>(tx, ty, tz, off, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.bigz, o.flip,
+        dda_advance<COLUMN>(tx, ty, tz, off, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.flip,
                            dtx, dty, dtz);
         w[u] = load_word(rs, off);
     }
@@ -318,7 +325,7 @@ __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buf
             part += fabsf(__uint_as_float(xs));
             if constexpr (COUNT) n += take ? 1u : 0u;
             run = run && (int)x >= 0;
-            dda_advance<BRICK>(tx, ty, tz, off, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.bigz, o.flip,
+            dda_advance<COLUMN>(tx, ty, tz, off, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.flip,
                                dtx, dty, dtz);
             w[u] = load_word(rs, off);
         }

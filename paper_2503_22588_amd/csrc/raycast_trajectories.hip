@@ -26,10 +26,10 @@ namespace nbt {
 // map offset: by dbx/dby/dbz per step on x/y/z.  Past the segment end it
 // drifts, but every slot from there on reads the sentinel and is never
 // marked, so it needs no gating.
-template <bool BRICK>
+template <bool COLUMN>
 __device__ __forceinline__ void dda_advance_idx(float& tx, float& ty, float& tz, uint32_t& off,
                                                 int& idx, bool& alive, float t1, int dxo, int dyo, int dzo,
-                                                int bxo, int byo, int bzo, uint32_t flip, int dbx, int dby,
+                                                int bxo, int byo, uint32_t flip, int dbx, int dby,
                                                 int dbz, float dtx, float dty, float dtz) {
     const float x = tx, y = ty, z = tz;
     const float tm = fminf(fminf(x, y), z);
@@ -38,11 +38,15 @@ __device__ __forceinline__ void dda_advance_idx(float& tx, float& ty, float& tz,
     const bool bx = go && ex;
     const bool by = go && !ex && ey;
     const bool bz = go && !ex && !ey;
-    int d = bx ? dxo : (by ? dyo : dzo);
-    if constexpr (BRICK) {
-        const uint32_t msk = bx ? 0x0Cu : (by ? 0x30u : 0xC0u);
-        const int big = bx ? bxo : (by ? byo : bzo);
-        d = ((off ^ flip) & msk) == 0u ? big : d;
+    int d;
+    if constexpr (COLUMN) {
+        const uint32_t msk = bx ? 0x0Cu : 0x30u;
+        const int big = bx ? bxo : byo;
+        const int small = bx ? dxo : dyo;
+        const int dxy = ((off ^ flip) & msk) == 0u ? big : small;
+        d = bz ? dzo : dxy;
+    } else {
+        d = bx ? dxo : (by ? dyo : dzo);
     }
     off = go ? off + (uint32_t)d : 0u;
     idx += bx ? dbx : (by ? dby : dbz);
@@ -65,11 +69,11 @@ __device__ __forceinline__ void dda_advance_idx(float& tx, float& ty, float& tz,
 // voxels is exactly the set visited.  CHECK = false sets every visit with an
 // atomic OR (for bitsets in global memory, where a read could be served by a
 // stale L1 line).  Returns the number of voxels visited.
-template <int P, bool CHECK, bool BRICK>
+template <int P, bool CHECK, bool COLUMN>
 __device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buffer_rsrc_t rs,
                                                   const RayState& r, int lx, int ly, int lz, int ax,
                                                   int ay, uint32_t nbits, uint32_t* bits) {
-    const OffsetSteps o = offset_steps<BRICK>(m, r);
+    const OffsetSteps o = offset_steps<COLUMN>(m, r);
     const int dbx = r.sx, dby = r.sy * ax, dbz = r.sz * ax * ay;
     const float dtx = r.dtx, dty = r.dty, dtz = r.dtz;
     const float t1 = r.t1;
@@ -85,7 +89,7 @@ __device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buff
     bi[0] = bidx;
 #pragma unroll
     for (int u = 1; u < P; ++u) {
-        dda_advance_idx<BRICK>(tx, ty, tz, off, bidx, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.bigz, o.flip,
+        dda_advance_idx<COLUMN>(tx, ty, tz, off, bidx, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.flip,
                                dbx, dby, dbz, dtx, dty, dtz);
         w[u] = load_word(rs, off);
         bi[u] = bidx;
@@ -113,7 +117,7 @@ __device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buff
             }
             n += take ? 1u : 0u;
             run = run && (int)x >= 0;
-            dda_advance_idx<BRICK>(tx, ty, tz, off, bidx, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.bigz, o.flip,
+            dda_advance_idx<COLUMN>(tx, ty, tz, off, bidx, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.flip,
                                dbx, dby, dbz, dtx, dty, dtz);
             w[u] = load_word(rs, off);
             bi[u] = bidx;
@@ -226,7 +230,7 @@ __global__ __launch_bounds__(WAVES * 64) void traj_union_kernel(
             RayState ray;
             const int st = setup_ray(m, c, pose, i, j, ray);
             if (st == kRayOk) {
-                if (m.layout == kLayoutBrick4)
+                if (m.layout == kLayoutColumn4)
                     steps += walk_ray_mark<4, !GLOBAL, true>(m, rs, ray, b.lx, b.ly, b.lz, b.ax, b.ay, b.nbits, bits);
                 else
                     steps += walk_ray_mark<4, !GLOBAL, false>(m, rs, ray, b.lx, b.ly, b.lz, b.ax, b.ay, b.nbits, bits);

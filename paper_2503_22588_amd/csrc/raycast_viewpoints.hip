@@ -67,7 +67,7 @@ __device__ __forceinline__ void vp_group(const DevMap& m, const CamParams& c,
             if (st == kRayOk) {
                 if constexpr (DEPTH == 1) {
                     walk_ray<false>(m, rs, ray, acc, steps, [](int, int, int) {});
-                } else if (m.layout == kLayoutBrick4) {      // uniform per workgroup
+                } else if (m.layout == kLayoutColumn4) {     // uniform per workgroup
                     walk_ray_pipelined<DEPTH, COUNT, true>(m, rs, ray, acc, steps);
                 } else {
                     walk_ray_pipelined<DEPTH, COUNT, false>(m, rs, ray, acc, steps);

@@ -34,7 +34,7 @@ def nbt():
     return nbt
 
 
-@pytest.fixture(scope="module", params=[0, 1], ids=["linear", "brick4"])
+@pytest.fixture(scope="module", params=[0, 1], ids=["linear", "column4"])
 def ctx(nbt, request):
     """Every test of this module runs once per map layout."""
     c = nbt.Context(0)
@@ -293,7 +293,7 @@ def test_layouts_bit_identical(nbt, ctx):
     out = {}
     before = ctx.get_map_layout()
     try:
-        for lay in (nbt.binding.LAYOUT_LINEAR, nbt.binding.LAYOUT_BRICK4):
+        for lay in (nbt.binding.LAYOUT_LINEAR, nbt.binding.LAYOUT_COLUMN4):
             ctx.set_map_layout(lay)
             m = _map(nbt, ctx, scene)
             assert m.info()["layout"] == lay
