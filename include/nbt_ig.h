@@ -234,8 +234,10 @@ int nbt_ig_trace_paths(const nbt_ig_map* map, const nbt_ig_camera* cam, const fl
  * deals runs of C consecutive workgroups (the workgroups of neighbouring
  * perspectives) to one XCD and its L2, 0 keeps the hardware's round-robin
  * order (C <= 65536); pipeline_depth in
- * {1,2,4,8} map gathers in flight per ray (0 = default).  Any shape gives
- * the same step counts; IG agrees to the last-place rounding of its sum.
+ * {1,2,4,8} map gathers in flight per ray (0 = default, 8).  A new context
+ * starts at 4 waves, 8x8 tiles, balanced tiles per wave, no remap, 8 gathers
+ * in flight.  Any shape gives the same step counts; IG agrees to the
+ * last-place rounding of its sum.
  */
 typedef struct {
     int32_t waves_per_group;

@@ -190,7 +190,7 @@ class Context:
         self.device = int(device)
         self._children = weakref.WeakSet()     # maps, batches and surrogates of this context
 
-    def set_launch(self, waves_per_group=8, tile_w_log2=3, tiles_per_wave=0, xcd_remap=0, pipeline_depth=0):
+    def set_launch(self, waves_per_group=4, tile_w_log2=3, tiles_per_wave=0, xcd_remap=0, pipeline_depth=0):
         _check(_lib.nbt_ig_ctx_set_launch(self.handle, C.byref(LaunchT(waves_per_group, tile_w_log2,
                                                                         tiles_per_wave, xcd_remap,
                                                                         pipeline_depth))))
@@ -402,7 +402,7 @@ class Batch:
                                      _dev_ptr(ig_out, torch.float32, "ig_out"),
                                      _dev_ptr(steps_out, torch.int64, "steps_out"), _stream(stream)))
 
-    def set_launch(self, waves_per_group=8, tile_w_log2=3, tiles_per_wave=0, pipeline_depth=0):
+    def set_launch(self, waves_per_group=4, tile_w_log2=3, tiles_per_wave=0, pipeline_depth=0):
         _check(_lib.nbt_ig_batch_set_launch(self.handle, C.byref(LaunchT(waves_per_group, tile_w_log2,
                                                                           tiles_per_wave, 0, pipeline_depth))))
 

@@ -49,7 +49,7 @@ struct nbt_ig_ctx {
     std::mutex mu;
     nbt::VpAccum* ws = nullptr;          // per-perspective reduction slots, kept zeroed
     size_t ws_cap = 0;              // slots allocated
-    nbt::VpLaunch vp_launch{8, 3, 0, 0, 4};  // 8 waves, 8x8 tiles, tiles/wave balanced per camera, no remap, 4 gathers in flight
+    nbt::VpLaunch vp_launch{4, 3, 0, 0, 8};  // 4 waves, 8x8 tiles, tiles/wave balanced per camera, no remap, 8 gathers in flight
     size_t lds_max = 0;             // device limit of LDS per workgroup (bytes)
     size_t lds_budget = 0;          // LDS a trajectory bitset may use (bytes)
     int traj_waves = 8;             // wavefronts per trajectory workgroup (4, 8, 16)

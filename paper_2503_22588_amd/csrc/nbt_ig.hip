@@ -529,7 +529,7 @@ int nbt_ig_ctx_set_launch(nbt_ig_ctx* ctx, const nbt_ig_launch* l) {
         return fail(NBT_IG_EINVAL, "tiles_per_wave must be in 0..4096 (got %d)", l->tiles_per_wave);
     if (l->xcd_remap < 0 || l->xcd_remap > 65536)
         return fail(NBT_IG_EINVAL, "xcd_remap must be in 0..65536 (got %d)", l->xcd_remap);
-    const int d = l->pipeline_depth == 0 ? 4 : l->pipeline_depth;
+    const int d = l->pipeline_depth == 0 ? 8 : l->pipeline_depth;
     if (!(d == 1 || d == 2 || d == 4 || d == 8))
         return fail(NBT_IG_EINVAL, "pipeline_depth must be 0 (default), 1, 2, 4 or 8 (got %d)", d);
     std::lock_guard<std::mutex> lk(ctx->mu);
