@@ -53,3 +53,19 @@ def test_context_creation_reports_missing_device():
     with pytest.raises(nbt.NbtError) as e:
         nbt.Context(0)
     assert e.value.status in (nbt.binding.EDEVICE, nbt.binding.EINVAL)
+
+
+def test_binding_constants_match_the_header():
+    """Every numeric constant the binding mirrors (status codes, ray end reasons, voxel states,
+    map layouts) has the header's value."""
+    import paper_2503_22588_amd as nbt
+    text = open(HEADER).read()
+    values = {name: int(v) for name, v in re.findall(r"\bNBT_IG_([A-Z0-9_]+)\s*=\s*(-?\d+)", text)}
+    checked = 0
+    for name, v in values.items():
+        if hasattr(nbt.binding, name):
+            assert getattr(nbt.binding, name) == v, name
+            checked += 1
+    for required in ("OK", "EINVAL", "RAY_HIT", "RAY_EXIT", "OCCUPIED", "LAYOUT_LINEAR", "LAYOUT_COLUMN4"):
+        assert required in values and hasattr(nbt.binding, required), required
+    assert checked >= 14
