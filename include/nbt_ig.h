@@ -186,7 +186,8 @@ int nbt_ig_eval_viewpoints(const nbt_ig_map* map, const nbt_ig_camera* cam, cons
  *   ig_union[t]    sum over U_t of the Eq. 2 gains (binary64, rounded once to
  *                  float32); NaN if any ray of the trajectory is INVALID;
  *   counts[4t+0..3] |U_t|, occupied, free and unknown voxels of U_t (exact);
- *   visits[t]      total voxel visits of all its rays (exact; may be NULL).
+ *   visits[t]      total voxel visits of all its rays (exact; may be NULL: the
+ *                  walk then keeps no per-ray visit count, which is faster).
  * Each trajectory's visited set is a bitset over the voxel box holding its
  * frusta, kept in LDS when it fits the context's LDS budget and in global
  * memory otherwise (allocated on demand).  The call synchronises `stream`

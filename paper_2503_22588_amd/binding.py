@@ -326,14 +326,15 @@ def eval_viewpoints(m: Map, cam, poses, ig_out=None, steps_out=None, stream=None
     return ig_out, steps_out
 
 
-def eval_trajectories(m: Map, cam, poses, stream=None):
-    """Union IG per trajectory: poses float32 [T, L, 12] -> (ig [T], counts [T,4] int32, visits [T] int64)."""
+def eval_trajectories(m: Map, cam, poses, stream=None, want_visits=True):
+    """Union IG per trajectory: poses float32 [T, L, 12] -> (ig [T], counts [T,4] int32, visits [T] int64
+    or None when want_visits is False: the walk then keeps no visit count, which is faster)."""
     torch = _torch()
     T, L = int(poses.shape[0]), int(poses.shape[1])
     dev = poses.device
     ig = torch.empty(T, dtype=torch.float32, device=dev)
     counts = torch.empty((T, 4), dtype=torch.int32, device=dev)
-    visits = torch.empty(T, dtype=torch.int64, device=dev)
+    visits = torch.empty(T, dtype=torch.int64, device=dev) if want_visits else None
     cm = camera(cam)
     _check(_lib.nbt_ig_eval_trajectories(m.handle, C.byref(cm), _dev_ptr(poses, torch.float32, "poses"), T, L,
                                          _dev_ptr(ig, torch.float32, "ig"), _dev_ptr(counts, None, "counts"),
@@ -477,16 +478,16 @@ def autotune_map(m: Map, cam, poses, ig_out=None, steps_out=None, stream=None):
     return _launch_dict(l), lay.value, ms.value
 
 
-def autotune_trajectories(m: Map, cam, poses, stream=None):
+def autotune_trajectories(m: Map, cam, poses, stream=None, want_visits=False):
     """Pick the storage order of the map (it is rewritten in it) and the trajectory workgroup
-    size (the context keeps it) that run eval_trajectories fastest on these poses [T, L, 12].
-    Returns (layout, waves, ms)."""
+    size (the context keeps it) that run eval_trajectories fastest on these poses [T, L, 12]
+    (timed without the visit count unless want_visits).  Returns (layout, waves, ms)."""
     torch = _torch()
     T, L = int(poses.shape[0]), int(poses.shape[1])
     dev = poses.device
     ig = torch.empty(T, dtype=torch.float32, device=dev)
     counts = torch.empty((T, 4), dtype=torch.int32, device=dev)
-    visits = torch.empty(T, dtype=torch.int64, device=dev)
+    visits = torch.empty(T, dtype=torch.int64, device=dev) if want_visits else None
     cm = camera(cam)
     lay, w, ms = C.c_int(), C.c_int(), C.c_float()
     _check(_lib.nbt_ig_autotune_trajectories(m.handle, C.byref(cm), _dev_ptr(poses, torch.float32, "poses"), T, L,

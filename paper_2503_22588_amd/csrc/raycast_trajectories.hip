@@ -68,8 +68,10 @@ __device__ __forceinline__ void dda_advance_idx(float& tx, float& ty, float& tz,
 // stale read can only show fewer bits than are set, so the set of marked
 // voxels is exactly the set visited.  CHECK = false sets every visit with an
 // atomic OR (for bitsets in global memory, where a read could be served by a
-// stale L1 line).  Returns the number of voxels visited.
-template <int P, bool CHECK, bool COLUMN>
+// stale L1 line).  Returns the number of voxels visited when COUNT is set
+// (0 otherwise: without a per-lane count the loop is guarded by a group
+// budget, as in walk_ray_pipelined).
+template <int P, bool CHECK, bool COLUMN, bool COUNT>
 __device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buffer_rsrc_t rs,
                                                   const RayState& r, int lx, int ly, int lz, int ax,
                                                   int ay, uint32_t nbits, uint32_t* bits) {
@@ -81,6 +83,7 @@ __device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buff
     int bidx = ((r.iz - lz) * ay + (r.iy - ly)) * ax + (r.ix - lx);
     float tx = r.tx, ty = r.ty, tz = r.tz;
     const uint32_t guard = (uint32_t)(m.nx + m.ny + m.nz + 3);
+    uint32_t budget = guard / P + 2;
     bool alive = true;
 
     uint32_t w[P];
@@ -115,14 +118,16 @@ __device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buff
             } else if (mark) {
                 atomicOr(&bits[(uint32_t)bi[u] >> 5], 1u << ((uint32_t)bi[u] & 31u));
             }
-            n += take ? 1u : 0u;
+            if constexpr (COUNT) n += take ? 1u : 0u;
             run = run && (int)x >= 0;
             dda_advance_idx<COLUMN>(tx, ty, tz, off, bidx, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.flip,
                                dbx, dby, dbz, dtx, dty, dtz);
             w[u] = load_word(rs, off);
             bi[u] = bidx;
         }
-        run = run && n < guard;      // the border bounds n below nx + ny + nz; guard only
+        // the border bounds the visits below nx + ny + nz; the guards only back that up
+        if constexpr (COUNT) run = run && n < guard;
+        else run = run && --budget != 0u;
     }
     if constexpr (CHECK)
         if (pend_mask & ~pend_seen) atomicOr(&bits[pend_word], pend_mask);
@@ -192,7 +197,7 @@ __global__ __launch_bounds__(256) void traj_box_kernel(DevMap m, CamParams c,
     boxes[t] = b;
 }
 
-template <bool GLOBAL, int WAVES>
+template <bool GLOBAL, int WAVES, bool COUNT>
 __global__ __launch_bounds__(WAVES * 64) void traj_union_kernel(
     DevMap m, CamParams c, const float* __restrict__ poses, uint32_t L,
     const TrajBox* __restrict__ boxes, const uint32_t* __restrict__ over_list,
@@ -231,9 +236,11 @@ __global__ __launch_bounds__(WAVES * 64) void traj_union_kernel(
             const int st = setup_ray(m, c, pose, i, j, ray);
             if (st == kRayOk) {
                 if (m.layout == kLayoutColumn4)
-                    steps += walk_ray_mark<4, !GLOBAL, true>(m, rs, ray, b.lx, b.ly, b.lz, b.ax, b.ay, b.nbits, bits);
+                    steps += walk_ray_mark<4, !GLOBAL, true, COUNT>(m, rs, ray, b.lx, b.ly, b.lz, b.ax, b.ay,
+                                                                    b.nbits, bits);
                 else
-                    steps += walk_ray_mark<4, !GLOBAL, false>(m, rs, ray, b.lx, b.ly, b.lz, b.ax, b.ay, b.nbits, bits);
+                    steps += walk_ray_mark<4, !GLOBAL, false, COUNT>(m, rs, ray, b.lx, b.ly, b.lz, b.ax, b.ay,
+                                                                     b.nbits, bits);
             } else if (st == kRayInvalid) {
                 invalid = true;
             }
@@ -307,7 +314,7 @@ __global__ __launch_bounds__(WAVES * 64) void traj_union_kernel(
 size_t traj_static_lds_bytes() {
     // the largest static LDS among the workgroup sizes (the 16-wave kernel)
     hipFuncAttributes a;
-    if (hipFuncGetAttributes(&a, (const void*)traj_union_kernel<false, 16>) != hipSuccess) return 4096;
+    if (hipFuncGetAttributes(&a, (const void*)traj_union_kernel<false, 16, true>) != hipSuccess) return 4096;
     return a.sharedSizeBytes;
 }
 
@@ -319,18 +326,18 @@ hipError_t launch_traj_boxes(const DevMap& m, const CamParams& c, const float* p
     return hipGetLastError();
 }
 
-template <bool GLOBAL, int WAVES>
+template <bool GLOBAL, int WAVES, bool COUNT>
 static hipError_t launch_union(const DevMap& m, const CamParams& c, const float* poses, uint32_t L,
                                uint32_t grid, size_t lds_bytes, const TrajBox* boxes,
                                const uint32_t* over_list, uint32_t* gbits, float* ig_union,
                                uint32_t* counts, unsigned long long* visits, hipStream_t s) {
-    const void* k = (const void*)traj_union_kernel<GLOBAL, WAVES>;
+    const void* k = (const void*)traj_union_kernel<GLOBAL, WAVES, COUNT>;
     if (!GLOBAL) {
         static std::atomic<size_t> lds_set[64];
         const hipError_t e = allow_dynamic_lds(k, lds_bytes, lds_set, 64);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((traj_union_kernel<GLOBAL, WAVES>), dim3(grid), dim3(WAVES * 64), GLOBAL ? 0 : lds_bytes,
+    hipLaunchKernelGGL((traj_union_kernel<GLOBAL, WAVES, COUNT>), dim3(grid), dim3(WAVES * 64), GLOBAL ? 0 : lds_bytes,
                        s, m, c, poses, L, boxes, over_list, gbits, ig_union, counts, visits);
     return hipGetLastError();
 }
@@ -340,12 +347,15 @@ hipError_t launch_traj_union(bool global, int waves, const DevMap& m, const CamP
                              const TrajBox* boxes, const uint32_t* over_list, uint32_t* gbits,
                              float* ig_union, uint32_t* counts, unsigned long long* visits,
                              hipStream_t s) {
-#define NBT_TU(G, W)                                                                              \
-    if (global == G && waves == W)                                                                \
-        return launch_union<G, W>(m, c, poses, L, grid, lds_bytes, boxes, over_list, gbits, ig_union, \
-                                  counts, visits, s);
-    NBT_TU(false, 4) NBT_TU(false, 8) NBT_TU(false, 16)
-    NBT_TU(true, 4) NBT_TU(true, 8) NBT_TU(true, 16)
+    const bool count = visits != nullptr;    // no visit count when the caller does not ask for it
+#define NBT_TU(G, W, C)                                                                              \
+    if (global == G && waves == W && count == C)                                                     \
+        return launch_union<G, W, C>(m, c, poses, L, grid, lds_bytes, boxes, over_list, gbits, ig_union, \
+                                     counts, visits, s);
+    NBT_TU(false, 4, true) NBT_TU(false, 8, true) NBT_TU(false, 16, true)
+    NBT_TU(true, 4, true) NBT_TU(true, 8, true) NBT_TU(true, 16, true)
+    NBT_TU(false, 4, false) NBT_TU(false, 8, false) NBT_TU(false, 16, false)
+    NBT_TU(true, 4, false) NBT_TU(true, 8, false) NBT_TU(true, 16, false)
 #undef NBT_TU
     return hipErrorInvalidValue;
 }

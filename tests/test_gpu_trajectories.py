@@ -86,6 +86,14 @@ def test_small_lds_path(nbt, ctx, small):
     with pytest.raises(nbt.NbtError):
         ctx.set_traj_waves(6)
     assert ref[1][:, 0].min() > 1000
+    # without visits the walk keeps no count; IG and counts are the same bits
+    import torch
+    ig, counts, visits = nbt.eval_trajectories(m, cam, _dev(traj), want_visits=False)
+    torch.cuda.synchronize()
+    assert visits is None
+    got = _run(nbt, m, cam, traj)
+    assert np.array_equal(ig.cpu().numpy().view(np.uint32), got[0].view(np.uint32))
+    assert np.array_equal(counts.cpu().numpy().astype(np.uint32), got[1])
 
 
 def test_small_global_and_mixed_paths(nbt, ctx, small):
@@ -96,6 +104,8 @@ def test_small_global_and_mixed_paths(nbt, ctx, small):
         _check(_run(nbt, m, cam, traj), ref)
         ctx.set_lds_budget(30 * 1024)         # some fit, some do not
         _check(_run(nbt, m, cam, traj), ref)
+        ig, counts, _ = nbt.eval_trajectories(m, cam, _dev(traj), want_visits=False)
+        assert np.array_equal(counts.cpu().numpy().astype(np.uint32), ref[1])
         ctx.set_traj_waves(4)
         _check(_run(nbt, m, cam, traj), ref)
     finally:
