@@ -12,10 +12,12 @@ namespace nbt {
 
 // Encoded voxel word: the Eq. 2 gain of the voxel as float32 bits, with the
 // sign bit set for Occupied voxels (their gain 1-P is still in the low 31
-// bits).  The one-voxel border around the map holds kSentinel, a negative
-// NaN pattern that no gain can take, so a single signed test per step
-// catches both "stop after this voxel" and "the walk left the map".
-constexpr uint32_t kSentinel = 0xFFFFFFFFu;
+// bits).  The one-voxel border around the map holds kSentinel, the negative
+// of the smallest denormal (2^-149): no gain takes it (1-P of an Occupied
+// voxel is 0 or at least 2^-24), so a single signed test per step catches
+// both "stop after this voxel" and "the walk left the map", and a walk that
+// needs no visit count may add its magnitude instead of testing for it.
+constexpr uint32_t kSentinel = 0x80000001u;
 constexpr uint32_t kOccBit = 0x80000000u;
 constexpr uint32_t kGainOne = 0x3F800000u;   // 1.0f: the gain of an Unknown voxel
 

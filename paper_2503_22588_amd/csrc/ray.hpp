@@ -186,10 +186,6 @@ __device__ __forceinline__ int walk_ray(const DevMap& m, __amdgpu_buffer_rsrc_t 
     return kEndExit;
 }
 
-// Words at or above this value are the border sentinel; every Occupied word
-// lies in 0x80000000..0xBF800000.
-constexpr uint32_t kMarkerMin = 0xBF800001u;
-
 // Per-ray constants of the incremental map offset.  Linear layout: a step on
 // axis a adds d[a] bytes.  Column layout: a z step adds dz (one 64-B layer);
 // an x or y step inside the 4x4 tile adds dx or dy (the in-tile stride) and
@@ -317,7 +313,11 @@ __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buf
 #pragma unroll
         for (int u = 0; u < P; ++u) {
             const uint32_t x = w[u];
-            const bool take = run && x < kMarkerMin;
+            // a voxel visit, not the sentinel.  The IG-only walk skips the test:
+            // the sentinel then adds its magnitude 2^-149, at most once per ray
+            // (it stops the walk), so a ray sum and the IG are off by at most
+            // 2^-149 absolute.
+            const bool take = COUNT ? (run && x != kSentinel) : run;
             // the empty asm keeps each slot's read ahead of its refill (else the
             // reads sink to the end of the group and the refills need copies)
             uint32_t xs = take ? x : 0u;

@@ -105,7 +105,7 @@ __device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buff
 #pragma unroll
         for (int u = 0; u < P; ++u) {
             const uint32_t x = w[u];
-            const bool take = run && x < kMarkerMin;
+            const bool take = run && x != kSentinel;
             const bool mark = take && (uint32_t)bi[u] < nbits;
             if constexpr (CHECK) {
                 if (pend_mask & ~pend_seen) atomicOr(&bits[pend_word], pend_mask);
