@@ -148,7 +148,7 @@ def extra_trajectories(nbt, ctx, reps):
             "ms_per_launch": ms, "trajectory_evals_per_s": traj.shape[0] / (ms * 1e-3),
             "rays_per_s": rays / (ms * 1e-3), "voxel_steps_per_s": vis / (ms * 1e-3),
             "mean_unique_voxels": float(counts[:, 0].float().mean().item()),
-            "map_layout": "column4" if layout == nbt.LAYOUT_COLUMN4 else "linear", "waves_per_group": waves,
+            "map_layout": nbt.LAYOUT_NAMES[layout], "waves_per_group": waves,
             "note": "timed without the visit count (its voxel steps come from one untimed counting call); "
                     "includes the box pre-pass and its one host synchronisation"}
 
@@ -175,7 +175,7 @@ def extra_batch(nbt, ctx, reps):
     res = {"workload": f"64 maps (sizes in {{64,96,128,192,256}}^3, 5 cm), {n} perspectives, 64x48 rays",
            "batch_latency_ms": ms, "viewpoint_evals_per_s": n / (ms * 1e-3), "rays_per_s": rays / (ms * 1e-3),
            "voxel_steps_per_s": steps / (ms * 1e-3), "launch": b.get_launch(),
-           "map_layout": ["linear", "column4"][layout]}
+           "map_layout": nbt.LAYOUT_NAMES[layout]}
     b.close()
     return res
 
@@ -296,7 +296,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default=None,
                     help="waves,tile_w_log2,tiles_per_wave,xcd_remap,pipeline_depth")
-    ap.add_argument("--layout", choices=("linear", "column4"), default=None,
+    ap.add_argument("--layout", choices=("linear", "column4", "column2", "column8"), default=None,
                     help="map storage order (default: the library's)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the trajectory and batched measurements")
@@ -358,7 +358,7 @@ def main():
     stream = torch.cuda.current_stream()
     ctx = nbt.Context(0)
     if args.layout:
-        ctx.set_map_layout({"linear": nbt.LAYOUT_LINEAR, "column4": nbt.LAYOUT_COLUMN4}[args.layout])
+        ctx.set_map_layout(nbt.LAYOUT_NAMES.index(args.layout))
     if args.launch:
         ctx.set_launch(*[int(v) for v in args.launch.split(",")])
     prob = torch.from_numpy(scene.P).cuda()
@@ -373,7 +373,7 @@ def main():
         # untimed set-up: the library picks the map's storage order and the launch shape
         t_tune = time.perf_counter()
         launch, layout, tune_ms = nbt.autotune_map(m, cam, dposes, ig_out=ig)
-        tuned = {"layout": ["linear", "column4"][layout], "launch": launch, "ms": tune_ms,
+        tuned = {"layout": nbt.LAYOUT_NAMES[layout], "launch": launch, "ms": tune_ms,
                  "seconds": time.perf_counter() - t_tune}
         _log(f"autotuned: {tuned}")
 
@@ -436,7 +436,7 @@ def main():
             "rays_per_perspective": cam.width * cam.height,
             "map": list(scene.P.shape[::-1]),
             "launch": ctx.get_launch(),
-            "map_layout": ["linear", "column4"][m.info()["layout"]],
+            "map_layout": nbt.LAYOUT_NAMES[m.info()["layout"]],
             "tuned_by": "nbt_ig_autotune_map (untimed set-up)" if tuned else "command line",
         },
         "rays_per_s": rays * args.steps / wall,

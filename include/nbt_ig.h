@@ -79,8 +79,10 @@ enum { NBT_IG_OCCUPIED = 1, NBT_IG_FREE = 2, NBT_IG_UNKNOWN = 3 };
 /* Device storage order of an encoded map (nbt_ig_ctx_set_map_layout). */
 enum {
     NBT_IG_LAYOUT_LINEAR = 0,   /* x fastest over the bordered grid */
-    NBT_IG_LAYOUT_COLUMN4 = 1   /* 4x4 columns: the x-y plane in 4x4 tiles (64 B, x fastest), a tile's
+    NBT_IG_LAYOUT_COLUMN4 = 1,  /* 4x4 columns: the x-y plane in 4x4 tiles (64 B, x fastest), a tile's
                                    layers stored z after z, tiles x fastest */
+    NBT_IG_LAYOUT_COLUMN2 = 2,  /* the same with 2x2 tiles (16 B per layer) */
+    NBT_IG_LAYOUT_COLUMN8 = 3   /* the same with 8x8 tiles (256 B per layer) */
 };
 
 typedef struct nbt_ig_ctx nbt_ig_ctx;
@@ -134,7 +136,7 @@ int nbt_ig_ctx_get_map_layout(const nbt_ig_ctx* ctx, int* layout);
  * voxel stores its Eq. 2 gain with the sign bit marking Occupied, inside a
  * one-voxel border that stops every ray leaving the map, stored in the
  * context's map layout.  1 <= n <= 4096 per axis and (nx+2)(ny+2)(nz+2) <
- * 2^30 (for 4x4 columns: the count with x and y padded to multiples of 4 < 2^30).  `origin` (HOST, 3 floats) is the world
+ * 2^30 (for the column orders: the count with x and y padded to whole tiles < 2^30).  `origin` (HOST, 3 floats) is the world
  * position of the min corner of voxel (0,0,0); `voxel_size` > 0 is s_Vox.
  * `cls` may be NULL (0.5/0.5); 0 <= free_threshold <= occ_threshold <= 1.
  * Probabilities outside [0,1] or NaN give NBT_IG_EINVAL (checked on the
@@ -299,15 +301,15 @@ int nbt_ig_batch_autotune(nbt_ig_batch* batch, const uint32_t* vp_offsets, const
                           float* best_ms);
 
 /* Chooses the storage order of the batch's maps (all alike): times the batch
- * in both orders at its current launch shape, leaves the maps in the faster
- * one (*best_layout, HOST; mean ms per run in *best_ms) and updates the
+ * in every storage order (linear and the three column tile sizes) at its
+ * current launch shape, leaves the maps in the fastest one (*best_layout, HOST; mean ms per run in *best_ms) and updates the
  * batch.  Synchronises `stream`; no other work may use the maps meanwhile.
  * NBT_IG_EINVAL when another batch holds one of the maps too. */
 int nbt_ig_batch_autotune_layout(nbt_ig_batch* batch, const uint32_t* vp_offsets, const float* poses,
                                  float* ig_out, uint64_t* steps_out, void* stream, int* best_layout,
                                  float* best_ms);
 
-/* For trajectory IG: times nbt_ig_eval_trajectories on both storage orders of
+/* For trajectory IG: times nbt_ig_eval_trajectories on every storage order of
  * the map and each trajectory workgroup size (4, 8, 16 waves), keeps the
  * fastest (the map rewritten in *best_layout, the context set to *best_waves;
  * HOST outputs, mean ms per call in *best_ms).  Outputs are written as by the
@@ -318,8 +320,8 @@ int nbt_ig_autotune_trajectories(nbt_ig_map* map, const nbt_ig_camera* cam, cons
                                  float* best_ms);
 
 /* As nbt_ig_autotune_viewpoints, and first the map's storage order: times
- * nbt_ig_eval_viewpoints on both orders at the context's launch shape, keeps
- * the map in the faster one (*best_layout, HOST; see nbt_ig_map_set_layout),
+ * nbt_ig_eval_viewpoints in every order at the context's launch shape, keeps
+ * the map in the fastest one (*best_layout, HOST; see nbt_ig_map_set_layout),
  * then searches the launch shape.  The map must not be held by a batch. */
 int nbt_ig_autotune_map(nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses, uint32_t n,
                         float* ig_out, uint64_t* steps_out, void* stream, nbt_ig_launch* best,

@@ -29,7 +29,8 @@ _lib = C.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
 RAY_MISS, RAY_HIT, RAY_END, RAY_EXIT, RAY_INVALID = 0, 1, 2, 3, 4
-LAYOUT_LINEAR, LAYOUT_COLUMN4 = 0, 1
+LAYOUT_LINEAR, LAYOUT_COLUMN4, LAYOUT_COLUMN2, LAYOUT_COLUMN8 = 0, 1, 2, 3
+LAYOUT_NAMES = ("linear", "column4", "column2", "column8")
 OCCUPIED, FREE, UNKNOWN = 1, 2, 3
 
 
@@ -206,7 +207,7 @@ class Context:
         _check(_lib.nbt_ig_ctx_set_lds_budget(self.handle, int(nbytes)))
 
     def set_map_layout(self, layout):
-        """Storage order of maps created from now on: LAYOUT_LINEAR or LAYOUT_COLUMN4."""
+        """Storage order of maps created from now on: LAYOUT_LINEAR or LAYOUT_COLUMN2/4/8."""
         _check(_lib.nbt_ig_ctx_set_map_layout(self.handle, int(layout)))
 
     def get_map_layout(self):

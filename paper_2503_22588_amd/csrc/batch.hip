@@ -111,6 +111,16 @@ nbt_ig_launch from_vp(const VpLaunch& v) {
     return nbt_ig_launch{v.waves, v.tile_w_log2, v.tiles_per_wave, v.xcd_remap, v.depth};
 }
 
+// The storage orders a layout autotuner tries (NBT_IG_LAYOUT_* are 0..3).
+constexpr int kLayouts = NBT_IG_LAYOUT_COLUMN8 + 1;
+
+int fastest_layout(const float* ms) {
+    int best = 0;
+    for (int l = 1; l < kLayouts; ++l)
+        if (ms[l] < ms[best]) best = l;
+    return best;
+}
+
 // Exhaustive search over the launch grid (3 x 3 x 3 x 3 = 81 shapes): every
 // shape is applied, run once untimed (warm-up, graph rebuild) and timed over
 // `reps` runs; the fastest is kept.  A search one parameter at a time was
@@ -312,7 +322,7 @@ int nbt_ig_batch_autotune_layout(nbt_ig_batch* b, const uint32_t* vp_offsets, co
         return NBT_IG_OK;
     };
     const int start = b->maps.empty() ? NBT_IG_LAYOUT_LINEAR : b->maps[0]->dm.layout;
-    float ms[2] = {0.0f, 0.0f};
+    float ms[kLayouts] = {};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return fail(NBT_IG_EDEVICE, "hipEventCreate failed");
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -320,8 +330,8 @@ int nbt_ig_batch_autotune_layout(nbt_ig_batch* b, const uint32_t* vp_offsets, co
         return fail(NBT_IG_EDEVICE, "hipEventCreate failed");
     }
     int rc = NBT_IG_OK;
-    for (int i = 0; i < 2 && rc == NBT_IG_OK; ++i) {
-        const int lay = i == 0 ? start : 1 - start;
+    for (int i = 0; i < kLayouts && rc == NBT_IG_OK; ++i) {
+        const int lay = (start + i) % kLayouts;        // the current order first
         rc = apply(lay);
         if (rc == NBT_IG_OK) rc = nbt_ig_batch_run(b, vp_offsets, poses, ig_out, steps_out, stream);
         hipError_t e = rc == NBT_IG_OK ? hipEventRecord(e0, s) : hipSuccess;
@@ -335,7 +345,7 @@ int nbt_ig_batch_autotune_layout(nbt_ig_batch* b, const uint32_t* vp_offsets, co
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != NBT_IG_OK) return rc;
-    const int lay = ms[NBT_IG_LAYOUT_COLUMN4] < ms[NBT_IG_LAYOUT_LINEAR] ? NBT_IG_LAYOUT_COLUMN4 : NBT_IG_LAYOUT_LINEAR;
+    const int lay = fastest_layout(ms);
     if (int r2 = apply(lay)) return r2;
     *best_layout = lay;
     *best_ms = ms[lay] / 3.0f;
@@ -364,8 +374,8 @@ int nbt_ig_autotune_trajectories(nbt_ig_map* map, const nbt_ig_camera* cam, cons
     int bl = map->dm.layout, bw = orig_waves;
     int rc = NBT_IG_OK;
     const int start = map->dm.layout;
-    for (int i = 0; i < 2 && rc == NBT_IG_OK; ++i) {
-        const int lay = i == 0 ? start : 1 - start;
+    for (int i = 0; i < kLayouts && rc == NBT_IG_OK; ++i) {
+        const int lay = (start + i) % kLayouts;        // the current order first
         rc = nbt_ig_map_set_layout(map, lay, stream);
         for (int w = 0; w < 3 && rc == NBT_IG_OK; ++w) {
             rc = nbt_ig_ctx_set_traj_waves(ctx, waves[w]);
@@ -413,7 +423,7 @@ int nbt_ig_autotune_map(nbt_ig_map* map, const nbt_ig_camera* cam, const float* 
     hipStream_t s = (hipStream_t)stream;
     // each layout at the context's current shape, then the shape search on the faster one
     const int start = map->dm.layout;
-    float ms[2] = {0.0f, 0.0f};
+    float ms[kLayouts] = {};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return fail(NBT_IG_EDEVICE, "hipEventCreate failed");
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -421,8 +431,8 @@ int nbt_ig_autotune_map(nbt_ig_map* map, const nbt_ig_camera* cam, const float* 
         return fail(NBT_IG_EDEVICE, "hipEventCreate failed");
     }
     int rc = NBT_IG_OK;
-    for (int i = 0; i < 2 && rc == NBT_IG_OK; ++i) {
-        const int lay = i == 0 ? start : 1 - start;
+    for (int i = 0; i < kLayouts && rc == NBT_IG_OK; ++i) {
+        const int lay = (start + i) % kLayouts;        // the current order first
         rc = nbt_ig_map_set_layout(map, lay, stream);
         if (rc == NBT_IG_OK) rc = nbt_ig_eval_viewpoints(map, cam, poses, n, ig_out, steps_out, stream);
         hipError_t e = rc == NBT_IG_OK ? hipEventRecord(e0, s) : hipSuccess;
@@ -436,7 +446,7 @@ int nbt_ig_autotune_map(nbt_ig_map* map, const nbt_ig_camera* cam, const float* 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != NBT_IG_OK) return rc;
-    const int lay = ms[NBT_IG_LAYOUT_COLUMN4] < ms[NBT_IG_LAYOUT_LINEAR] ? NBT_IG_LAYOUT_COLUMN4 : NBT_IG_LAYOUT_LINEAR;
+    const int lay = fastest_layout(ms);
     if (int r2 = nbt_ig_map_set_layout(map, lay, stream)) return r2;
     *best_layout = lay;
     return nbt_ig_autotune_viewpoints(map, cam, poses, n, ig_out, steps_out, stream, best, best_ms);

@@ -24,15 +24,23 @@ constexpr uint32_t kGainOne = 0x3F800000u;   // 1.0f: the gain of an Unknown vox
 // Storage order of the encoded words over the padded grid (X, Y, Z) =
 // (x+1, y+1, z+1):
 //   kLayoutLinear  x fastest: (Z*py + Y)*px + X;
-//   kLayoutColumn4 4x4 columns: the x-y plane is cut into 4x4 tiles of 16
-//                  words (64 B, x fastest), each tile stores its layers z
-//                  after z, and tiles go x fastest over the tile grid:
-//                  ((Y/4*nbx + X/4)*pz + Z)*16 + (Y%4)*4 + X%4.
-//                  A 128-B line holds a 4x4x2 block and four aligned layers
-//                  a contiguous 4x4x4 block (256 B); a z step is always +-64 B.
+//   column orders  T x T columns (T = 2, 4, 8): the x-y plane is cut into
+//                  T x T tiles of T*T words (x fastest), each tile stores
+//                  its layers z after z, and tiles go x fastest over the
+//                  tile grid: ((Y/T*nbx + X/T)*pz + Z)*T*T + (Y%T)*T + X%T.
+//                  For T = 4 a 128-B line holds a 4x4x2 block and four
+//                  aligned layers a contiguous 4x4x4 block (256 B); a z step
+//                  is always one layer.
 // Padding of x and y up to whole tiles holds the sentinel as well.
 constexpr int kLayoutLinear = NBT_IG_LAYOUT_LINEAR;
-constexpr int kLayoutColumn4 = NBT_IG_LAYOUT_COLUMN4;
+
+// log2 of the tile edge of a column order; 0 for the linear order.
+__host__ __device__ inline int layout_tile_log2(int layout) {
+    return layout == NBT_IG_LAYOUT_COLUMN2 ? 1
+         : layout == NBT_IG_LAYOUT_COLUMN4 ? 2
+         : layout == NBT_IG_LAYOUT_COLUMN8 ? 3 : 0;
+}
+inline bool valid_layout(int layout) { return layout >= NBT_IG_LAYOUT_LINEAR && layout <= NBT_IG_LAYOUT_COLUMN8; }
 
 // Device view of an encoded map (passed to kernels by value).
 struct DevMap {
@@ -40,8 +48,9 @@ struct DevMap {
     uint32_t bytes;         // size of enc in bytes (< 2^32)
     int nx, ny, nz;         // real dimensions
     int px, py, pz;         // padded dimensions (n + 2)
-    int layout;             // kLayoutLinear or kLayoutColumn4
-    int nbx, nby;           // tiles per axis over the padded x-y plane (kLayoutColumn4)
+    int layout;             // NBT_IG_LAYOUT_*
+    int tl;                 // log2 of the tile edge of a column order, 0 for the linear order
+    int nbx, nby;           // tiles per axis over the padded x-y plane (column orders)
     float inv_s;            // 1/voxel_size (binary32)
     float ox, oy, oz;       // origin
 };
@@ -50,9 +59,10 @@ struct DevMap {
 // included), in either layout.
 __host__ __device__ inline uint32_t voxel_offset(const DevMap& m, int x, int y, int z) {
     const uint32_t X = (uint32_t)(x + 1), Y = (uint32_t)(y + 1), Z = (uint32_t)(z + 1);
-    if (m.layout == kLayoutLinear) return ((Z * (uint32_t)m.py + Y) * (uint32_t)m.px + X) * 4u;
-    const uint32_t tile = (Y >> 2) * (uint32_t)m.nbx + (X >> 2);
-    return ((tile * (uint32_t)m.pz + Z) * 16u + ((Y & 3u) << 2 | (X & 3u))) * 4u;
+    if (m.tl == 0) return ((Z * (uint32_t)m.py + Y) * (uint32_t)m.px + X) * 4u;
+    const uint32_t t = (uint32_t)m.tl, lo = (1u << t) - 1u;
+    const uint32_t tile = (Y >> t) * (uint32_t)m.nbx + (X >> t);
+    return (((tile * (uint32_t)m.pz + Z) << (2u * t)) + ((Y & lo) << t | (X & lo))) * 4u;
 }
 
 // Endpoint-grid parameters derived once per launch on the host.

@@ -3,7 +3,7 @@
 // Each voxel is classified once (Occupied if P > occ, Free if P < free,
 // Unknown otherwise) and stored as its Eq. 2 gain (1-P, P or 1) in float32
 // bits, with the sign bit set for Occupied.  A one-voxel border of sentinel
-// words surrounds the map (and fills the tile padding of the column layout).  The
+// words surrounds the map (and fills the tile padding of the column orders).  The
 // walk then needs one 4-byte gather and one signed compare per voxel: no
 // probability, no threshold and no bounds test is evaluated per step.
 // Streaming kernel, about 8 B per voxel.
@@ -30,17 +30,18 @@ __device__ __forceinline__ uint32_t encode_word(const float* __restrict__ prob, 
 
 // Padded coordinates of stored word idx.
 __device__ __forceinline__ void word_coords(const DevMap& m, uint32_t idx, uint32_t& X, uint32_t& Y, uint32_t& Z) {
-    if (m.layout == kLayoutLinear) {
+    if (m.tl == 0) {
         X = idx % (uint32_t)m.px;
         const uint32_t yz = idx / (uint32_t)m.px;
         Y = yz % (uint32_t)m.py;
         Z = yz / (uint32_t)m.py;
     } else {
-        const uint32_t r = idx >> 4, l = idx & 15u;
+        const uint32_t t = (uint32_t)m.tl;
+        const uint32_t r = idx >> (2u * t), l = idx & ((1u << (2u * t)) - 1u);
         Z = r % (uint32_t)m.pz;
         const uint32_t tile = r / (uint32_t)m.pz;
-        X = (tile % (uint32_t)m.nbx) * 4 + (l & 3u);
-        Y = (tile / (uint32_t)m.nbx) * 4 + (l >> 2);
+        X = ((tile % (uint32_t)m.nbx) << t) + (l & ((1u << t) - 1u));
+        Y = ((tile / (uint32_t)m.nbx) << t) + (l >> t);
     }
 }
 

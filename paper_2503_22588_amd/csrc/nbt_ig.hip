@@ -120,6 +120,20 @@ int check_map(const nbt_ig_map* map) {
     return NBT_IG_OK;
 }
 
+// Sets the storage order of dm (px, py, pz given) and returns its word count.
+uint64_t set_layout_geometry(DevMap& dm, int layout) {
+    dm.layout = layout;
+    dm.tl = layout_tile_log2(layout);
+    if (dm.tl == 0) {
+        dm.nbx = dm.nby = 0;
+        return (uint64_t)dm.px * dm.py * dm.pz;
+    }
+    const int T = 1 << dm.tl;
+    dm.nbx = (dm.px + T - 1) >> dm.tl;
+    dm.nby = (dm.py + T - 1) >> dm.tl;
+    return (uint64_t)dm.nbx * dm.nby * (uint64_t)(T * T) * dm.pz;
+}
+
 }  // namespace nbt
 
 // ---------------------------------------------------------------- API -------
@@ -130,9 +144,7 @@ int relayout_map(nbt_ig_map* map, int layout, hipStream_t s) {
     DeviceGuard g(map->ctx->device);
     if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", map->ctx->device);
     DevMap nd = map->dm;
-    nd.layout = layout;
-    const uint64_t words = layout == NBT_IG_LAYOUT_COLUMN4 ? (uint64_t)nd.nbx * nd.nby * 16 * nd.pz
-                                                           : (uint64_t)nd.px * nd.py * nd.pz;
+    const uint64_t words = set_layout_geometry(nd, layout);
     if (words >= (1ull << 30)) return fail(NBT_IG_EUNSUPPORTED, "map too large for this layout");
     uint32_t* enc = nullptr;
     hipError_t e = hipMalloc(&enc, words * 4);
@@ -223,9 +235,9 @@ int nbt_ig_create_map(nbt_ig_ctx* ctx, const float* prob, int nx, int ny, int nz
     if (nx < 1 || ny < 1 || nz < 1 || nx > 4096 || ny > 4096 || nz > 4096)
         return fail(NBT_IG_EINVAL, "map dims %dx%dx%d outside [1, 4096]", nx, ny, nz);
     const int layout = ctx->map_layout;
-    const int nbx = (nx + 2 + 3) / 4, nby = (ny + 2 + 3) / 4;
-    const uint64_t padded = layout == NBT_IG_LAYOUT_COLUMN4 ? (uint64_t)nbx * nby * 16 * (uint64_t)(nz + 2)
-                                                            : (uint64_t)(nx + 2) * (ny + 2) * (nz + 2);
+    DevMap geo{};
+    geo.px = nx + 2; geo.py = ny + 2; geo.pz = nz + 2;
+    const uint64_t padded = set_layout_geometry(geo, layout);
     if (padded >= (1ull << 30))
         return fail(NBT_IG_EUNSUPPORTED, "map %dx%dx%d: padded size must stay below 2^30 voxels", nx, ny, nz);
     if (!finite_pos(voxel_size)) return fail(NBT_IG_EINVAL, "voxel_size must be finite and > 0");
@@ -256,8 +268,8 @@ int nbt_ig_create_map(nbt_ig_ctx* ctx, const float* prob, int nx, int ny, int nz
     dm.bytes = (uint32_t)map->enc_bytes;
     dm.nx = nx; dm.ny = ny; dm.nz = nz;
     dm.px = nx + 2; dm.py = ny + 2; dm.pz = nz + 2;
-    dm.layout = layout;
-    dm.nbx = nbx; dm.nby = nby;
+    dm.layout = geo.layout; dm.tl = geo.tl;
+    dm.nbx = geo.nbx; dm.nby = geo.nby;
     dm.inv_s = 1.0f / voxel_size;
     dm.ox = origin[0]; dm.oy = origin[1]; dm.oz = origin[2];
 
@@ -429,7 +441,7 @@ int nbt_ig_ctx_set_lds_budget(nbt_ig_ctx* ctx, size_t bytes) {
 
 int nbt_ig_ctx_set_map_layout(nbt_ig_ctx* ctx, int layout) {
     if (!ctx) return fail(NBT_IG_EINVAL, "ctx is NULL");
-    if (layout != NBT_IG_LAYOUT_LINEAR && layout != NBT_IG_LAYOUT_COLUMN4)
+    if (!valid_layout(layout))
         return fail(NBT_IG_EINVAL, "unknown map layout %d", layout);
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->map_layout = layout;
@@ -444,7 +456,7 @@ int nbt_ig_ctx_get_map_layout(const nbt_ig_ctx* ctx, int* layout) {
 
 int nbt_ig_map_set_layout(nbt_ig_map* map, int layout, void* stream) {
     if (int rc = check_map(map)) return rc;
-    if (layout != NBT_IG_LAYOUT_LINEAR && layout != NBT_IG_LAYOUT_COLUMN4)
+    if (!valid_layout(layout))
         return fail(NBT_IG_EINVAL, "unknown map layout %d", layout);
     {
         std::lock_guard<std::mutex> lk(map->ctx->mu);

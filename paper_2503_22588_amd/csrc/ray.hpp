@@ -187,36 +187,42 @@ __device__ __forceinline__ int walk_ray(const DevMap& m, __amdgpu_buffer_rsrc_t 
 }
 
 // Per-ray constants of the incremental map offset.  Linear layout: a step on
-// axis a adds d[a] bytes.  Column layout: a z step adds dz (one 64-B layer);
-// an x or y step inside the 4x4 tile adds dx or dy (the in-tile stride) and
-// one across a tile face adds bigx or bigy.  The step crosses when the
-// voxel's in-tile coordinate on that axis is 3 (forward) or 0 (backward),
-// i.e. when ((off ^ flip) & mask) == 0, with the in-tile x and y in bits 2-3
-// and 4-5 of the byte offset and flip holding 3 in the fields of the forward
-// axes.
+// axis a adds d[a] bytes.  Column orders (T x T tiles, T = 1 << TL): a z step
+// adds dz (one layer of T*T words); an x or y step inside the tile adds dx or
+// dy (the in-tile stride) and one across a tile face adds bigx or bigy.  The
+// step crosses when the voxel's in-tile coordinate on that axis is T-1
+// (forward) or 0 (backward), i.e. when ((off ^ flip) & mask) == 0, with the
+// in-tile x and y in the fields tile_mask_x/y of the byte offset (TL bits
+// each, from bit 2) and flip holding T-1 in the fields of the forward axes.
 struct OffsetSteps {
     int dx, dy, dz;
     int bigx, bigy;
     uint32_t flip;
 };
 
-template <bool COLUMN>
+template <int TL> constexpr uint32_t tile_mask_x() { return ((1u << TL) - 1u) << 2; }
+template <int TL> constexpr uint32_t tile_mask_y() { return ((1u << TL) - 1u) << (2 + TL); }
+
+// TL: 0 for the linear order, else log2 of the column tile edge (m.tl).
+template <int TL>
 __device__ __forceinline__ OffsetSteps offset_steps(const DevMap& m, const RayState& r) {
     OffsetSteps o;
-    if constexpr (!COLUMN) {
+    if constexpr (TL == 0) {
         o.dx = r.sx * 4;
         o.dy = r.sy * m.px * 4;
         o.dz = r.sz * m.px * m.py * 4;
         o.bigx = o.bigy = 0;
         o.flip = 0;
     } else {
-        const int column = 64 * m.pz;          // bytes of one tile's column
+        constexpr int T = 1 << TL;
+        constexpr int layer = 4 * T * T;       // bytes of one layer of a tile
+        const int column = layer * m.pz;       // bytes of one tile's column
         o.dx = r.sx * 4;
-        o.dy = r.sy * 16;
-        o.dz = r.sz * 64;
-        o.bigx = r.sx * (column - 12);
-        o.bigy = r.sy * (column * m.nbx - 48);
-        o.flip = (r.sx > 0 ? 0x0Cu : 0u) | (r.sy > 0 ? 0x30u : 0u);
+        o.dy = r.sy * 4 * T;
+        o.dz = r.sz * layer;
+        o.bigx = r.sx * (column - 4 * (T - 1));
+        o.bigy = r.sy * (column * m.nbx - 4 * T * (T - 1));
+        o.flip = (r.sx > 0 ? tile_mask_x<TL>() : 0u) | (r.sy > 0 ? tile_mask_y<TL>() : 0u);
     }
     return o;
 }
@@ -228,7 +234,7 @@ __device__ __forceinline__ OffsetSteps offset_steps(const DevMap& m, const RaySt
 // loaded value ever being inspected here (which would force a wait for it).
 // Loop invariants are passed by value so that the axis choice stays a
 // register select.
-template <bool COLUMN>
+template <int TL>
 __device__ __forceinline__ void dda_advance(float& tx, float& ty, float& tz, uint32_t& off,
                                             bool& alive, float t1, int dxo, int dyo, int dzo,
                                             int bxo, int byo, uint32_t flip,
@@ -241,10 +247,10 @@ __device__ __forceinline__ void dda_advance(float& tx, float& ty, float& tz, uin
     const bool by = go && !ex && ey;
     const bool bz = go && !ex && !ey;
     int d;
-    if constexpr (COLUMN) {
+    if constexpr (TL != 0) {
         // x or y: the in-tile stride, or the tile-crossing delta at the tile
         // face; z: one layer.  Two selects fewer than a 3-axis edge test.
-        const uint32_t msk = bx ? 0x0Cu : 0x30u;
+        const uint32_t msk = bx ? tile_mask_x<TL>() : tile_mask_y<TL>();
         const int big = bx ? bxo : byo;
         const int small = bx ? dxo : dyo;
         const int dxy = ((off ^ flip) & msk) == 0u ? big : small;
@@ -270,14 +276,14 @@ __device__ __forceinline__ void dda_advance(float& tx, float& ty, float& tz, uin
 // order are exactly those of walk_ray (the sum is rounded differently, see
 // below); only the reason is not reported, and the visit count only when
 // COUNT is set.  Gathers past a stop are never
-// consumed (and out-of-range ones read 0).  COLUMN selects the map layout.
+// consumed (and out-of-range ones read 0).  TL selects the map order (see offset_steps).
 constexpr uint32_t kRunSlots = 8;
 
-template <int P, bool COUNT, bool COLUMN>
+template <int P, bool COUNT, int TL>
 __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buffer_rsrc_t rs,
                                                    const RayState& r, double& acc, uint32_t& steps) {
     static_assert(P == 2 || P == 4 || P == 8, "pipeline depth");
-    const OffsetSteps o = offset_steps<COLUMN>(m, r);
+    const OffsetSteps o = offset_steps<TL>(m, r);
     const float dtx = r.dtx, dty = r.dty, dtz = r.dtz;
     const float t1 = r.t1;
     uint32_t off = voxel_offset(m, r.ix, r.iy, r.iz);
@@ -288,7 +294,7 @@ __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buf
     w[0] = load_word(rs, off);
 #pragma unroll
     for (int u = 1; u < P; ++u) {
-        dda_advance<COLUMN>(tx, ty, tz, off, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.flip,
+        dda_advance<TL>(tx, ty, tz, off, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.flip,
                            dtx, dty, dtz);
         w[u] = load_word(rs, off);
     }
@@ -325,7 +331,7 @@ __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buf
             part += fabsf(__uint_as_float(xs));
             if constexpr (COUNT) n += take ? 1u : 0u;
             run = run && (int)x >= 0;
-            dda_advance<COLUMN>(tx, ty, tz, off, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.flip,
+            dda_advance<TL>(tx, ty, tz, off, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.flip,
                                dtx, dty, dtz);
             w[u] = load_word(rs, off);
         }

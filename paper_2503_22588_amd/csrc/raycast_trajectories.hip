@@ -26,7 +26,7 @@ namespace nbt {
 // map offset: by dbx/dby/dbz per step on x/y/z.  Past the segment end it
 // drifts, but every slot from there on reads the sentinel and is never
 // marked, so it needs no gating.
-template <bool COLUMN>
+template <int TL>
 __device__ __forceinline__ void dda_advance_idx(float& tx, float& ty, float& tz, uint32_t& off,
                                                 int& idx, bool& alive, float t1, int dxo, int dyo, int dzo,
                                                 int bxo, int byo, uint32_t flip, int dbx, int dby,
@@ -39,8 +39,8 @@ __device__ __forceinline__ void dda_advance_idx(float& tx, float& ty, float& tz,
     const bool by = go && !ex && ey;
     const bool bz = go && !ex && !ey;
     int d;
-    if constexpr (COLUMN) {
-        const uint32_t msk = bx ? 0x0Cu : 0x30u;
+    if constexpr (TL != 0) {
+        const uint32_t msk = bx ? tile_mask_x<TL>() : tile_mask_y<TL>();
         const int big = bx ? bxo : byo;
         const int small = bx ? dxo : dyo;
         const int dxy = ((off ^ flip) & msk) == 0u ? big : small;
@@ -71,11 +71,11 @@ __device__ __forceinline__ void dda_advance_idx(float& tx, float& ty, float& tz,
 // stale L1 line).  Returns the number of voxels visited when COUNT is set
 // (0 otherwise: without a per-lane count the loop is guarded by a group
 // budget, as in walk_ray_pipelined).
-template <int P, bool CHECK, bool COLUMN, bool COUNT>
+template <int P, bool CHECK, int TL, bool COUNT>
 __device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buffer_rsrc_t rs,
                                                   const RayState& r, int lx, int ly, int lz, int ax,
                                                   int ay, uint32_t nbits, uint32_t* bits) {
-    const OffsetSteps o = offset_steps<COLUMN>(m, r);
+    const OffsetSteps o = offset_steps<TL>(m, r);
     const int dbx = r.sx, dby = r.sy * ax, dbz = r.sz * ax * ay;
     const float dtx = r.dtx, dty = r.dty, dtz = r.dtz;
     const float t1 = r.t1;
@@ -92,7 +92,7 @@ __device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buff
     bi[0] = bidx;
 #pragma unroll
     for (int u = 1; u < P; ++u) {
-        dda_advance_idx<COLUMN>(tx, ty, tz, off, bidx, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.flip,
+        dda_advance_idx<TL>(tx, ty, tz, off, bidx, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.flip,
                                dbx, dby, dbz, dtx, dty, dtz);
         w[u] = load_word(rs, off);
         bi[u] = bidx;
@@ -120,7 +120,7 @@ __device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buff
             }
             if constexpr (COUNT) n += take ? 1u : 0u;
             run = run && (int)x >= 0;
-            dda_advance_idx<COLUMN>(tx, ty, tz, off, bidx, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.flip,
+            dda_advance_idx<TL>(tx, ty, tz, off, bidx, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.flip,
                                dbx, dby, dbz, dtx, dty, dtz);
             w[u] = load_word(rs, off);
             bi[u] = bidx;
@@ -235,12 +235,23 @@ __global__ __launch_bounds__(WAVES * 64) void traj_union_kernel(
             RayState ray;
             const int st = setup_ray(m, c, pose, i, j, ray);
             if (st == kRayOk) {
-                if (m.layout == kLayoutColumn4)
-                    steps += walk_ray_mark<4, !GLOBAL, true, COUNT>(m, rs, ray, b.lx, b.ly, b.lz, b.ax, b.ay,
-                                                                    b.nbits, bits);
-                else
-                    steps += walk_ray_mark<4, !GLOBAL, false, COUNT>(m, rs, ray, b.lx, b.ly, b.lz, b.ax, b.ay,
-                                                                     b.nbits, bits);
+                switch (m.tl) {                  // the map's order; uniform per workgroup
+                case 1:
+                    steps += walk_ray_mark<4, !GLOBAL, 1, COUNT>(m, rs, ray, b.lx, b.ly, b.lz, b.ax, b.ay, b.nbits,
+                                                                 bits);
+                    break;
+                case 2:
+                    steps += walk_ray_mark<4, !GLOBAL, 2, COUNT>(m, rs, ray, b.lx, b.ly, b.lz, b.ax, b.ay, b.nbits,
+                                                                 bits);
+                    break;
+                case 3:
+                    steps += walk_ray_mark<4, !GLOBAL, 3, COUNT>(m, rs, ray, b.lx, b.ly, b.lz, b.ax, b.ay, b.nbits,
+                                                                 bits);
+                    break;
+                default:
+                    steps += walk_ray_mark<4, !GLOBAL, 0, COUNT>(m, rs, ray, b.lx, b.ly, b.lz, b.ax, b.ay, b.nbits,
+                                                                 bits);
+                }
             } else if (st == kRayInvalid) {
                 invalid = true;
             }

@@ -67,10 +67,13 @@ __device__ __forceinline__ void vp_group(const DevMap& m, const CamParams& c,
             if (st == kRayOk) {
                 if constexpr (DEPTH == 1) {
                     walk_ray<false>(m, rs, ray, acc, steps, [](int, int, int) {});
-                } else if (m.layout == kLayoutColumn4) {     // uniform per workgroup
-                    walk_ray_pipelined<DEPTH, COUNT, true>(m, rs, ray, acc, steps);
                 } else {
-                    walk_ray_pipelined<DEPTH, COUNT, false>(m, rs, ray, acc, steps);
+                    switch (m.tl) {          // the map's order; uniform per workgroup
+                    case 1: walk_ray_pipelined<DEPTH, COUNT, 1>(m, rs, ray, acc, steps); break;
+                    case 2: walk_ray_pipelined<DEPTH, COUNT, 2>(m, rs, ray, acc, steps); break;
+                    case 3: walk_ray_pipelined<DEPTH, COUNT, 3>(m, rs, ray, acc, steps); break;
+                    default: walk_ray_pipelined<DEPTH, COUNT, 0>(m, rs, ray, acc, steps);
+                    }
                 }
             } else if (st == kRayInvalid) {
                 invalid = true;

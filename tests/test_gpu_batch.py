@@ -28,7 +28,7 @@ def nbt():
     return nbt
 
 
-@pytest.fixture(scope="module", params=[0, 1], ids=["linear", "column4"])
+@pytest.fixture(scope="module", params=[0, 1, 2, 3], ids=["linear", "column4", "column2", "column8"])
 def ctx(nbt, request):
     """Every test of this module runs once per map layout."""
     c = nbt.Context(0)
@@ -149,7 +149,7 @@ def test_batch_launch_shapes_and_autotune(nbt, ctx, uneven):
     best, ms = b.autotune(off, dp, ig, st)
     assert ms > 0 and best["waves_per_group"] in (2, 4, 8)
     lay, lms = b.autotune_layout(off, dp, ig, st)          # maps rewritten; results unchanged
-    assert lay in (0, 1) and lms > 0 and all(m.info()["layout"] == lay for m in maps)
+    assert lay in (0, 1, 2, 3) and lms > 0 and all(m.info()["layout"] == lay for m in maps)
     b.run(off, dp, ig, st)
     torch.cuda.synchronize()
     assert np.array_equal(st.cpu().numpy(), st_single)

@@ -30,7 +30,7 @@ def nbt():
     return nbt
 
 
-@pytest.fixture(scope="module", params=[0, 1], ids=["linear", "column4"])
+@pytest.fixture(scope="module", params=[0, 1, 2, 3], ids=["linear", "column4", "column2", "column8"])
 def ctx(nbt, request):
     """Every test of this module runs once per map layout."""
     c = nbt.Context(0)

@@ -34,7 +34,7 @@ def nbt():
     return nbt
 
 
-@pytest.fixture(scope="module", params=[0, 1], ids=["linear", "column4"])
+@pytest.fixture(scope="module", params=[0, 1, 2, 3], ids=["linear", "column4", "column2", "column8"])
 def ctx(nbt, request):
     """Every test of this module runs once per map layout."""
     c = nbt.Context(0)
@@ -285,7 +285,7 @@ def test_argument_errors(nbt, ctx):
 
 
 def test_layouts_bit_identical(nbt, ctx):
-    """The two storage orders give the same bits for IG, step counts and ray digests."""
+    """Every storage order gives the same bits for IG, step counts and ray digests."""
     import torch
     w = make_config(1)
     scene, cam, poses = w.maps[0], w.camera, w.poses[0]
@@ -293,7 +293,7 @@ def test_layouts_bit_identical(nbt, ctx):
     out = {}
     before = ctx.get_map_layout()
     try:
-        for lay in (nbt.binding.LAYOUT_LINEAR, nbt.binding.LAYOUT_COLUMN4):
+        for lay in (0, 1, 2, 3):
             ctx.set_map_layout(lay)
             m = _map(nbt, ctx, scene)
             assert m.info()["layout"] == lay
@@ -305,14 +305,15 @@ def test_layouts_bit_identical(nbt, ctx):
             m.close()
     finally:
         ctx.set_map_layout(before)
-    for a, b in zip(out[0], out[1]):
-        assert np.array_equal(a, b)
+    for lay in (1, 2, 3):
+        for a, b in zip(out[0], out[lay]):
+            assert np.array_equal(a, b), lay
     with pytest.raises(nbt.NbtError):
-        ctx.set_map_layout(2)
+        ctx.set_map_layout(4)
 
 
 def test_relayout_and_layout_autotune(nbt, ctx):
-    """Rewriting a map in the other order keeps every result bit; the layout autotuner leaves
+    """Rewriting a map in another order keeps every result bit; the layout autotuner leaves
     the map in one of the two orders with the same results; a batch pins the order."""
     import torch
     w = make_config(1)
@@ -324,7 +325,7 @@ def test_relayout_and_layout_autotune(nbt, ctx):
     d0 = nbt.trace_rays(m, cam, dp)
     torch.cuda.synchronize()
     start = m.info()["layout"]
-    for lay in (1 - start, start, 1 - start):
+    for lay in ((start + 1) % 4, (start + 2) % 4, (start + 3) % 4, start):
         m.set_layout(lay)
         assert m.info()["layout"] == lay
         ig, st = nbt.eval_viewpoints(m, cam, dp)
@@ -336,7 +337,7 @@ def test_relayout_and_layout_autotune(nbt, ctx):
     before = ctx.get_launch()
     try:
         launch, lay, ms = nbt.autotune_map(m, cam, dp)
-        assert lay in (0, 1) and m.info()["layout"] == lay and ms > 0
+        assert lay in (0, 1, 2, 3) and m.info()["layout"] == lay and ms > 0
         ig, st = nbt.eval_viewpoints(m, cam, dp)
         torch.cuda.synchronize()
         assert np.array_equal(ig.cpu().numpy().view(np.uint32), ig0.cpu().numpy().view(np.uint32))
@@ -345,9 +346,9 @@ def test_relayout_and_layout_autotune(nbt, ctx):
                                              "xcd_remap", "pipeline_depth")])
     b = nbt.Batch(ctx, [m], cam, 64)
     with pytest.raises(nbt.NbtError):
-        m.set_layout(1 - m.info()["layout"])
+        m.set_layout((m.info()["layout"] + 1) % 4)
     b.close()
-    m.set_layout(1 - m.info()["layout"])        # allowed again once the batch is gone
+    m.set_layout((m.info()["layout"] + 1) % 4)  # allowed again once the batch is gone
     m.close()
 
 
