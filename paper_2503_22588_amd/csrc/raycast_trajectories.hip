@@ -61,14 +61,19 @@ __device__ __forceinline__ void dda_advance_idx(float& tx, float& ty, float& tz,
 // Pipelined walk that also sets, in `bits`, the bit of every visited voxel of
 // the box [lo, lo + (ax, ay, *)): ((z-lz)*ay + (y-ly))*ax + (x-lx).  Indices
 // at or beyond nbits (a voxel outside the box, impossible when the box
-// contains the ray's frustum) are skipped.  Along a trajectory almost every
-// visit finds its bit already set, so a slot reads the word and only an unset
-// bit costs an atomic OR; the read of slot u is checked one slot later, which
-// keeps its latency off the walk.  Setting a bit twice is harmless, and a
-// stale read can only show fewer bits than are set, so the set of marked
-// voxels is exactly the set visited.  CHECK = false sets every visit with an
-// atomic OR (for bitsets in global memory, where a read could be served by a
-// stale L1 line).  Returns the number of voxels visited when COUNT is set
+// contains the ray's frustum) are not counted.  Along a trajectory almost
+// every visit finds its bit already set, so a slot reads the word and only an
+// unset bit costs an atomic OR; the read of slot u is checked one slot later,
+// which keeps its latency off the walk.  Setting a bit twice is harmless, and
+// a stale read can only show fewer bits than are set, so the set of marked
+// voxels is exactly the set visited.  With CHECK the bitset is preceded by
+// one all-ones word (bits[-1]): a slot that marks nothing reads it and never
+// calls for the atomic, and an index at or beyond nbits is clamped to bit
+// nbits (the bitset has nbits / 32 + 1 words, so that bit exists), which the
+// epilogue ignores -- one select per slot instead of two selects, a compare
+// and a mask operation.  CHECK = false sets
+// every visit with an atomic OR (for bitsets in global memory, where a read
+// could be served by a stale L1 line).  Returns the number of voxels visited when COUNT is set
 // (0 otherwise: without a per-lane count the loop is guarded by a group
 // budget, as in walk_ray_pipelined).
 template <int P, bool CHECK, int TL, bool COUNT>
@@ -99,23 +104,24 @@ __device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buff
     }
     uint32_t n = 0;
     bool run = true;
-    uint32_t pend_word = 0, pend_mask = 0, pend_seen = 0;    // the previous slot's mark
+    int pend_word = -1;                                       // the previous slot's mark
+    uint32_t pend_mask = 0, pend_seen = 0;
     // Same slot structure as walk_ray_pipelined.
     while (run) {
 #pragma unroll
         for (int u = 0; u < P; ++u) {
             const uint32_t x = w[u];
             const bool take = run && x != kSentinel;
-            const bool mark = take && (uint32_t)bi[u] < nbits;
             if constexpr (CHECK) {
                 if (pend_mask & ~pend_seen) atomicOr(&bits[pend_word], pend_mask);
-                pend_word = mark ? (uint32_t)bi[u] >> 5 : 0u;
-                pend_mask = mark ? 1u << ((uint32_t)bi[u] & 31u) : 0u;
+                const uint32_t b = min((uint32_t)bi[u], nbits);
+                pend_word = take ? (int)(b >> 5) : -1;
+                pend_mask = 1u << (b & 31u);
                 pend_seen = bits[pend_word];
                 // keep this slot's generator step after the read, so that the
                 // read has the step's latency to complete before it is checked
                 __builtin_amdgcn_sched_barrier(0);
-            } else if (mark) {
+            } else if (take && (uint32_t)bi[u] < nbits) {
                 atomicOr(&bits[(uint32_t)bi[u] >> 5], 1u << ((uint32_t)bi[u] & 31u));
             }
             if constexpr (COUNT) n += take ? 1u : 0u;
@@ -207,10 +213,12 @@ __global__ __launch_bounds__(WAVES * 64) void traj_union_kernel(
     const uint32_t t = GLOBAL ? over_list[blockIdx.x] : blockIdx.x;
     const TrajBox b = boxes[t];
     if (!GLOBAL && b.global) return;
-    uint32_t* bits = GLOBAL ? gbits + b.goff : lds_bits;
-    const uint32_t nwords = (b.nbits + 31) / 32;
+    // in LDS the bitset follows the walk's all-ones word and holds bit nbits
+    uint32_t* bits = GLOBAL ? gbits + b.goff : lds_bits + 1;
+    const uint32_t nwords = GLOBAL ? (b.nbits + 31) / 32 : b.nbits / 32 + 1;
     const uint32_t tid = threadIdx.x;
     for (uint32_t w = tid; w < nwords; w += blockDim.x) bits[w] = 0u;
+    if (!GLOBAL && tid == 0) lds_bits[0] = ~0u;
     __syncthreads();
 
     const int wave = tid >> 6, lane = tid & 63;
@@ -266,6 +274,8 @@ __global__ __launch_bounds__(WAVES * 64) void traj_union_kernel(
     for (uint32_t w = tid; w < nwords; w += blockDim.x) {
         uint32_t word = GLOBAL ? __hip_atomic_load(&bits[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                                : bits[w];
+        // bits at or beyond nbits (the walk's clamp target) are not voxels of the box
+        if (w == b.nbits >> 5) word &= (1u << (b.nbits & 31u)) - 1u;
         while (word) {
             const int bit = __ffs(word) - 1;
             word &= word - 1u;
@@ -332,8 +342,14 @@ size_t traj_static_lds_bytes() {
 hipError_t launch_traj_boxes(const DevMap& m, const CamParams& c, const float* poses, uint32_t T,
                              uint32_t L, uint32_t budget_bits, TrajBox* boxes, TrajMeta* meta,
                              uint32_t* over_list, hipStream_t s) {
+    // budget_bits is the LDS a bitset may take.  An LDS bitset of b bits has
+    // b / 32 + 1 words after the walk's all-ones word, at most
+    // ceil(b / 32) * 4 + 8 bytes (launch_union adds the 8): boxes are routed
+    // to LDS only while that fits.
+    const uint32_t words = budget_bits / 32;
+    const uint32_t fit_bits = words > 2 ? (words - 2) * 32 : 0;
     hipLaunchKernelGGL(traj_box_kernel, dim3((T + 255) / 256), dim3(256), 0, s, m, c, poses, T, L,
-                       budget_bits, boxes, meta, over_list);
+                       fit_bits, boxes, meta, over_list);
     return hipGetLastError();
 }
 
@@ -343,12 +359,15 @@ static hipError_t launch_union(const DevMap& m, const CamParams& c, const float*
                                const uint32_t* over_list, uint32_t* gbits, float* ig_union,
                                uint32_t* counts, unsigned long long* visits, hipStream_t s) {
     const void* k = (const void*)traj_union_kernel<GLOBAL, WAVES, COUNT>;
+    // lds_bytes covers ceil(max_bits / 32) words; the all-ones word and the
+    // word that holds bit max_bits come on top
+    const size_t lds = GLOBAL ? 0 : lds_bytes + 8;
     if (!GLOBAL) {
         static std::atomic<size_t> lds_set[64];
-        const hipError_t e = allow_dynamic_lds(k, lds_bytes, lds_set, 64);
+        const hipError_t e = allow_dynamic_lds(k, lds, lds_set, 64);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((traj_union_kernel<GLOBAL, WAVES, COUNT>), dim3(grid), dim3(WAVES * 64), GLOBAL ? 0 : lds_bytes,
+    hipLaunchKernelGGL((traj_union_kernel<GLOBAL, WAVES, COUNT>), dim3(grid), dim3(WAVES * 64), lds,
                        s, m, c, poses, L, boxes, over_list, gbits, ig_union, counts, visits);
     return hipGetLastError();
 }
