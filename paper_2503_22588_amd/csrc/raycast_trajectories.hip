@@ -203,8 +203,11 @@ __global__ __launch_bounds__(256) void traj_box_kernel(DevMap m, CamParams c,
     boxes[t] = b;
 }
 
+// Eight waves per SIMD: the kernel fits 64 VGPRs, and left to itself the
+// compiler took 106 SGPRs, which allow only seven; with the hint it keeps 78
+// (the few spills are outside the walk) and four 8-wave workgroups fit a CU.
 template <bool GLOBAL, int WAVES, bool COUNT>
-__global__ __launch_bounds__(WAVES * 64) void traj_union_kernel(
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(8, 8))) void traj_union_kernel(
     DevMap m, CamParams c, const float* __restrict__ poses, uint32_t L,
     const TrajBox* __restrict__ boxes, const uint32_t* __restrict__ over_list,
     uint32_t* __restrict__ gbits, float* __restrict__ ig_union, uint32_t* __restrict__ counts,
