@@ -13,6 +13,7 @@ import pytest
 import oracle
 from workloads import look_at, make_config, scene_spheres, trajectories_walk
 from workloads.configs import Camera
+from workloads.scenes import SceneMap
 
 pytestmark = pytest.mark.gpu
 
@@ -175,6 +176,39 @@ def test_edge_cases(nbt, ctx, small):
     away = look_at(np.array([[-5.0, -5.0, -5.0]] * 2), np.array([-9.0, -9.0, -9.0]))[None]
     out = _run(nbt, m, cam, away)
     assert np.all(out[1] == 0) and out[0][0] == 0.0
+
+
+@pytest.mark.parametrize("shape", [(31, 1, 1), (8, 4, 1), (11, 3, 1), (4, 4, 4), (16, 4, 2), (9, 7, 5)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_whole_map_boxes(nbt, ctx, shape):
+    """Tiny maps seen whole from every pose: each trajectory's box is the whole map, so its
+    bitset has nx*ny*nz bits, on and beside multiples of 32 (the last word of an LDS bitset and
+    the bit that out-of-box indices are clamped to).  Also the LDS budget at the exact fit of
+    the box, one word under it (global path) and the default."""
+    nx, ny, nz = shape
+    _note(f"trajectories: whole-map boxes {shape}")
+    rng = np.random.default_rng(4100 + 97 * nx + 13 * ny + nz)
+    P = rng.choice(np.array([0.05, 0.2, 0.35, 0.5, 0.9], np.float32), size=(nz, ny, nx),
+                   p=[0.1, 0.3, 0.15, 0.4, 0.05])
+    voxel = 0.1
+    origin = np.array([0.3, -0.2, 0.1], np.float32)
+    centre = origin.astype(np.float64) + 0.5 * voxel * np.array([nx, ny, nz], np.float64)
+    sc = SceneMap(P=P, voxel=voxel, origin=origin, poi=centre)
+    cam = Camera(23, 17, 100.0, 90.0, 8.0)
+    d = rng.normal(size=(12, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    traj = look_at(centre + 2.5 * d, centre).reshape(3, 4, 12)
+    ref = oracle.eval_trajectories(sc, cam, traj)
+    assert np.all(ref[1][:, 0] > 0)
+    m = nbt.Map(ctx, sc.P, sc.voxel, sc.origin)
+    nbits = nx * ny * nz
+    fit = (-(-nbits // 32) + 2) * 4    # ceil(nbits / 32) words, room for the clamp bit, the all-ones word
+    try:
+        for budget in (0, fit, fit - 4):
+            ctx.set_lds_budget(budget)
+            _check(_run(nbt, m, cam, traj), ref)
+    finally:
+        ctx.set_lds_budget(0)
 
 
 def test_cfg4_full_size_sampled(nbt, ctx):
