@@ -61,21 +61,25 @@ __device__ __forceinline__ void dda_advance_idx(float& tx, float& ty, float& tz,
 // Pipelined walk that also sets, in `bits`, the bit of every visited voxel of
 // the box [lo, lo + (ax, ay, *)): ((z-lz)*ay + (y-ly))*ax + (x-lx).  Indices
 // at or beyond nbits (a voxel outside the box, impossible when the box
-// contains the ray's frustum) are not counted.  Along a trajectory almost
-// every visit finds its bit already set, so a slot reads the word and only an
-// unset bit costs an atomic OR; the read of slot u is checked one slot later,
-// which keeps its latency off the walk.  Setting a bit twice is harmless, and
-// a stale read can only show fewer bits than are set, so the set of marked
-// voxels is exactly the set visited.  With CHECK the bitset is preceded by
-// one all-ones word (bits[-1]): a slot that marks nothing reads it and never
-// calls for the atomic, and an index at or beyond nbits is clamped to bit
-// nbits (the bitset has nbits / 32 + 1 words, so that bit exists), which the
-// epilogue ignores -- one select per slot instead of two selects, a compare
-// and a mask operation.  CHECK = false sets
-// every visit with an atomic OR (for bitsets in global memory, where a read
-// could be served by a stale L1 line).  Returns the number of voxels visited when COUNT is set
-// (0 otherwise: without a per-lane count the loop is guarded by a group
-// budget, as in walk_ray_pipelined).
+// contains the ray's frustum) are not counted.
+//
+// CHECK (bitsets in LDS): along a trajectory almost every visit finds its bit
+// already set, so a slot reads the word and only an unset bit costs an atomic
+// OR; the read of slot u is checked one slot later, which keeps its latency
+// off the walk.  Setting a bit twice is harmless, and a stale read can only
+// show fewer bits than are set, so the set of marked voxels is exactly the set
+// visited.  The bitset is preceded by one all-ones word (bits[-1]): a slot
+// that marks nothing reads it and never calls for the atomic.  An index at or
+// beyond nbits is clamped to bit nbits (the bitset has nbits / 32 + 1 words,
+// so that bit exists), which the epilogue ignores.  One select per slot, where
+// a compare, two selects and a mask operation would otherwise decide the mark.
+//
+// CHECK = false (bitsets in global memory, where a read could be served by a
+// stale L1 line): every visit sets its bit with an atomic OR.
+//
+// Returns the number of voxels visited when COUNT is set (0 otherwise:
+// without a per-lane count the loop is guarded by a group budget, as in
+// walk_ray_pipelined).
 template <int P, bool CHECK, int TL, bool COUNT>
 __device__ __forceinline__ uint32_t walk_ray_mark(const DevMap& m, __amdgpu_buffer_rsrc_t rs,
                                                   const RayState& r, int lx, int ly, int lz, int ax,
