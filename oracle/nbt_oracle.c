@@ -51,6 +51,27 @@
  *       visits nothing and makes its perspective's IG NaN.
  *   C8  Trajectory union: the set of voxels visited by any ray of any pose
  *       of the trajectory; each counts once.
+ *
+ * Map update by depth-image insertion (the occupancy update that precedes
+ * IG evaluation, Sec. II-III: the map is built from the camera's point
+ * clouds; the paper delegates it to UfoMap and gives no formulas, so the
+ * standard log-odds occupancy update with clamping is written out here):
+ *   I1  Scan k = a pose plus a W x H depth image; D[j][i] is the z-depth in
+ *       metres of the return along pixel (i, j)'s ray of C1-C3 (that ray's
+ *       endpoint lies at z-depth d_Cam), so the return sits at segment
+ *       parameter s = D / d_Cam (one binary32 division).
+ *   I2  D not a number or D <= 0: no measurement, the ray is skipped.
+ *       s >= 1 (D = +inf included): no return within range; the segment
+ *       [0, 1] is carved free and nothing is hit.
+ *   I3  Otherwise the segment is [0, s]: the walk of C4-C6 with t1 replaced
+ *       by min(t1, s) and without the occupied stop.  If s <= t1 (the return
+ *       lies inside the map) the last voxel of the walk is hit and the
+ *       others are free; otherwise every voxel of the walk is free.
+ *   I4  Per scan (discrete insertion): H = voxels hit by any ray, F = voxels
+ *       free for any ray and not in H.  Each log-odds value L is updated
+ *       once per scan: L + l_hit on H, L + l_miss on F, then clamped as
+ *       min(max(L', l_min), l_max), all in binary32; other voxels keep L.
+ *   I5  Scans are applied in order.
  */
 #include <math.h>
 #include <stdint.h>
@@ -351,5 +372,142 @@ int oracle_eval_trajectories(const oracle_map* m, const oracle_camera* cam, cons
     free(seen);
     free(path);
     free(list);
+    return 0;
+}
+
+/*
+ * Log-odds occupancy update from depth images (I1-I5).  Only the geometry
+ * of *m is used (not m->P).  logodds: [nz][ny][nx], updated in place.
+ * Returns 0, or -1 when out of memory.
+ */
+int oracle_insert_scans(const oracle_map* m, const oracle_camera* cam, const float* poses,
+                        const float* depth, int64_t n_scans, float l_hit, float l_miss,
+                        float l_min, float l_max, float* logodds)
+{
+    enum { MARK_FREE = 1, MARK_HIT = 2 };
+    const int n[3] = {m->nx, m->ny, m->nz};
+    const int64_t nvox = (int64_t)m->nx * m->ny * m->nz;
+    uint8_t* mark = (uint8_t*)calloc((size_t)(nvox > 0 ? nvox : 1), 1);
+    if (!mark)
+        return -1;
+    const float dh = cam->range * cam->tan_half_h;
+    const float dv = cam->range * cam->tan_half_v;
+    const float inv_s = 1.0f / m->voxel;
+    const int guard = m->nx + m->ny + m->nz + 3;
+
+    for (int64_t k = 0; k < n_scans; ++k) {
+        const float* pose = poses + 12 * k;
+        const float* img = depth + k * (int64_t)cam->width * cam->height;
+        for (int j = 0; j < cam->height; ++j) {
+            for (int i = 0; i < cam->width; ++i) {
+                /* I1, I2: the measurement and the segment end */
+                const float d = img[(int64_t)j * cam->width + i];
+                if (!(d > 0.0f))
+                    continue; /* no measurement (NaN fails the test too) */
+                const float s = d / cam->range;
+                const int ret = s < 1.0f; /* a return within range */
+
+                /* C1-C3: the pixel's ray, as in oracle_cast_ray */
+                float u = 0.0f, v = 0.0f;
+                if (cam->width > 1)
+                    u = dh * ((float)(2 * i - (cam->width - 1)) / (float)(cam->width - 1));
+                if (cam->height > 1)
+                    v = dv * ((float)(2 * j - (cam->height - 1)) / (float)(cam->height - 1));
+                const float c[3] = {u, v, cam->range};
+                float O[3], E[3], D[3];
+                int finite = 1;
+                for (int a = 0; a < 3; ++a) {
+                    const float* row = pose + 3 * a;
+                    float w = row[0] * c[0];
+                    w = w + row[1] * c[1];
+                    w = w + row[2] * c[2];
+                    const float t = pose[9 + a];
+                    const float e = t + w;
+                    O[a] = (t - m->origin[a]) * inv_s;
+                    E[a] = (e - m->origin[a]) * inv_s;
+                    D[a] = E[a] - O[a];
+                    finite = finite && is_finite_f(O[a]) && is_finite_f(E[a]) && is_finite_f(D[a]);
+                }
+                if (!finite)
+                    continue; /* C7: an invalid ray updates nothing */
+
+                /* C4: clip to the map box and to [0, 1] */
+                float t0 = 0.0f, t1 = 1.0f;
+                float inv[3];
+                int parallel[3], miss = 0;
+                for (int a = 0; a < 3; ++a) {
+                    parallel[a] = fabsf(D[a]) < 0x1p-100f;
+                    if (parallel[a]) {
+                        if (!(O[a] >= 0.0f && O[a] < (float)n[a]))
+                            miss = 1;
+                        inv[a] = 0.0f;
+                        continue;
+                    }
+                    inv[a] = 1.0f / D[a];
+                    const float tA = (0.0f - O[a]) * inv[a];
+                    const float tB = ((float)n[a] - O[a]) * inv[a];
+                    t0 = sel_max(t0, sel_min(tA, tB));
+                    t1 = sel_min(t1, sel_max(tA, tB));
+                }
+                /* I3: the segment ends at the return when there is one */
+                const int inside = ret && s <= t1;
+                if (ret)
+                    t1 = sel_min(t1, s);
+                if (miss || t0 > t1)
+                    continue;
+
+                /* C5 */
+                int idx[3], step[3];
+                float tmax[3], tdelta[3];
+                for (int a = 0; a < 3; ++a) {
+                    float f = floorf(O[a] + t0 * D[a]);
+                    f = sel_max(f, 0.0f);
+                    f = sel_min(f, (float)(n[a] - 1));
+                    idx[a] = (int)f;
+                    if (parallel[a]) {
+                        step[a] = 0;
+                        tmax[a] = INFINITY;
+                        tdelta[a] = INFINITY;
+                    } else {
+                        step[a] = D[a] > 0.0f ? 1 : -1;
+                        tdelta[a] = fabsf(inv[a]);
+                        tmax[a] = ((float)(idx[a] + (step[a] > 0 ? 1 : 0)) - O[a]) * inv[a];
+                    }
+                }
+
+                /* C6 without the occupied stop; the last voxel is hit if I3 says so */
+                for (int visited = 0; visited < guard; ++visited) {
+                    const int64_t lin = ((int64_t)idx[2] * m->ny + idx[1]) * m->nx + idx[0];
+                    int a;
+                    if (tmax[0] <= tmax[1] && tmax[0] <= tmax[2])
+                        a = 0;
+                    else if (tmax[1] <= tmax[2])
+                        a = 1;
+                    else
+                        a = 2;
+                    if (tmax[a] > t1) {
+                        mark[lin] |= inside ? MARK_HIT : MARK_FREE;
+                        break;
+                    }
+                    mark[lin] |= MARK_FREE;
+                    idx[a] += step[a];
+                    if (idx[a] < 0 || idx[a] >= n[a])
+                        break;
+                    tmax[a] = tmax[a] + tdelta[a];
+                }
+            }
+        }
+        /* I4: one update per marked voxel, hit before free */
+        for (int64_t q = 0; q < nvox; ++q) {
+            if (!mark[q])
+                continue;
+            float l = logodds[q] + ((mark[q] & MARK_HIT) ? l_hit : l_miss);
+            l = sel_max(l, l_min);
+            l = sel_min(l, l_max);
+            logodds[q] = l;
+            mark[q] = 0;
+        }
+    }
+    free(mark);
     return 0;
 }

@@ -48,6 +48,9 @@ void oracle_eval_viewpoints(const oracle_map* m, const oracle_camera* cam, const
 int oracle_eval_trajectories(const oracle_map* m, const oracle_camera* cam, const float* poses,
                              int64_t n_traj, int64_t poses_per_traj, float* ig_union,
                              uint32_t* counts, uint64_t* visits);
+int oracle_insert_scans(const oracle_map* m, const oracle_camera* cam, const float* poses,
+                        const float* depth, int64_t n_scans, float l_hit, float l_miss,
+                        float l_min, float l_max, float* logodds);
 
 #ifdef __cplusplus
 }

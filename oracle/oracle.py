@@ -66,6 +66,10 @@ def lib():
             L.oracle_eval_trajectories.argtypes = [C.POINTER(OracleMap), C.POINTER(OracleCamera),
                                                    C.c_void_p, C.c_int64, C.c_int64,
                                                    C.c_void_p, C.c_void_p, C.c_void_p]
+            L.oracle_insert_scans.restype = C.c_int
+            L.oracle_insert_scans.argtypes = [C.POINTER(OracleMap), C.POINTER(OracleCamera),
+                                              C.c_void_p, C.c_void_p, C.c_int64, C.c_float,
+                                              C.c_float, C.c_float, C.c_float, C.c_void_p]
             _lib = L
     return _lib
 
@@ -165,3 +169,33 @@ def eval_trajectories(scene, camera, poses, thresholds=(0.5, 0.5)):
     if rc != 0:
         raise MemoryError("oracle_eval_trajectories: out of memory")
     return ig, counts, visits
+
+
+# Log-odds increments and clamping bounds of the occupancy update: the common
+# defaults of octree occupancy maps (hit 0.7, miss 0.4, clamped to
+# [0.1192, 0.971] in probability), as binary32 log-odds.
+DEFAULT_INSERT_PARAMS = tuple(float(np.float32(np.log(p / (1.0 - p)))) for p in (0.7, 0.4, 0.1192, 0.971))
+
+
+def insert_scans(geometry, camera, poses, depth, logodds, params=DEFAULT_INSERT_PARAMS):
+    """Depth-image insertion (I1-I5 of nbt_oracle.c): returns the updated copy of ``logodds``
+    [nz, ny, nx].  ``geometry`` supplies the grid (its P only for the shape), ``poses`` [K, 12],
+    ``depth`` [K, H, W] z-depths in metres; ``params`` = (l_hit, l_miss, l_min, l_max)."""
+    L = np.array(logodds, dtype=np.float32, copy=True, order="C")
+    m = _map(geometry) if hasattr(geometry, "P") else _map(L, *geometry)
+    cam = _cam(camera)
+    poses = np.ascontiguousarray(poses, dtype=np.float32).reshape(-1, 12)
+    depth = np.ascontiguousarray(depth, dtype=np.float32).reshape(poses.shape[0], cam.height, cam.width)
+    assert L.shape == (m.s.nz, m.s.ny, m.s.nx)
+    hit, miss, lo, hi = (float(np.float32(v)) for v in params)
+    rc = lib().oracle_insert_scans(C.byref(m.s), C.byref(cam), _ptr(poses), _ptr(depth), poses.shape[0],
+                                   hit, miss, lo, hi, _ptr(L))
+    if rc != 0:
+        raise MemoryError("oracle_insert_scans: out of memory")
+    return L
+
+
+def logodds_to_prob(L):
+    """P = 1 / (1 + exp(-L)) in binary64, rounded once to binary32."""
+    L = np.asarray(L, dtype=np.float64)
+    return (1.0 / (1.0 + np.exp(-L))).astype(np.float32)
