@@ -156,6 +156,50 @@ void nbt_ig_destroy_map(nbt_ig_map* map);        /* NULL is a no-op */
  * and returns NBT_IG_EINVAL if any update since the last check saw one.
  * Evaluations already enqueued on other streams must finish first. */
 int nbt_ig_update_map(nbt_ig_map* map, const float* prob, void* stream);
+
+/* ---- map update by depth-image insertion ----------------------------------------
+ * The occupancy update that precedes IG evaluation: the map is built from the
+ * camera's point clouds (Sec. II-III; the paper leaves it to its mapping
+ * library, so the usual clamped log-odds update is used).  A scan is a pose
+ * and a width x height z-depth image taken with the camera of the endpoint
+ * grid: the return of pixel (i, j) lies on that pixel's endpoint ray at
+ * parameter s = depth / range.  Depth NaN or <= 0: no measurement; s >= 1:
+ * no return within range (the whole segment is carved free).  The walk is the
+ * IG walk (same voxels, same tie rule) ending at the return and not stopping
+ * at occupied voxels; its last voxel is hit if the return lies inside the
+ * map, the others are free.  Per scan each marked voxel's log-odds value L
+ * moves once, by l_hit if any ray hit it, else by l_miss, and is clamped to
+ * [l_min, l_max] (binary32: add, then max, then min).  Scans apply in order.
+ */
+typedef struct {
+    float l_hit, l_miss;        /* log-odds increments of a hit and of a pass-through */
+    float l_min, l_max;         /* clamping bounds, l_min <= l_max, all finite */
+} nbt_ig_insert_params;
+
+/* log(p/(1-p)) of hit 0.7, miss 0.4 and the bounds 0.1192 / 0.971, in binary32. */
+nbt_ig_insert_params nbt_ig_insert_default_params(void);
+
+/* 32-bit words of the device workspace nbt_ig_insert_scans needs for `map`
+ * (one mark byte per voxel); 0 for NULL. */
+uint64_t nbt_ig_insert_workspace_words(const nbt_ig_map* map);
+
+/* Inserts n_scans scans into the log-odds grid of `map`'s geometry.
+ *   poses     DEVICE float [n_scans][12] (row-major R camera->world, then t)
+ *   depth     DEVICE float [n_scans][height][width], z-depth in metres
+ *   params    HOST, NULL = nbt_ig_insert_default_params()
+ *   logodds   DEVICE float [nz][ny][nx] (x fastest), updated in place
+ *   prob_out  DEVICE float [nz][ny][nx] or NULL: 1/(1+exp(-L)) of the result,
+ *             for nbt_ig_update_map (within a few binary32 ulp of the exact logistic)
+ *   workspace DEVICE uint32 [workspace_words] >= nbt_ig_insert_workspace_words(map),
+ *             all zero before the first call; every call leaves it zero.  Owned
+ *             by the caller; calls that share it must not overlap.
+ * Asynchronous on `stream` (two launches per scan).  The map's encoded words
+ * are not touched.  NBT_IG_EINVAL for NULL pointers, a short workspace or bad
+ * parameters. */
+int nbt_ig_insert_scans(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                        const float* depth, uint32_t n_scans, const nbt_ig_insert_params* params,
+                        float* logodds, float* prob_out, uint32_t* workspace,
+                        uint64_t workspace_words, void* stream);
 int nbt_ig_map_check(nbt_ig_map* map, void* stream);
 
 /* Dimensions of a map (HOST outputs, any may be NULL). */

@@ -50,6 +50,10 @@ class LaunchT(C.Structure):
                 ("tiles_per_wave", C.c_int32), ("xcd_remap", C.c_int32), ("pipeline_depth", C.c_int32)]
 
 
+class InsertParamsT(C.Structure):
+    _fields_ = [("l_hit", C.c_float), ("l_miss", C.c_float), ("l_min", C.c_float), ("l_max", C.c_float)]
+
+
 class ClassifyT(C.Structure):
     _fields_ = [("occ_threshold", C.c_float), ("free_threshold", C.c_float)]
 
@@ -74,6 +78,10 @@ _sig("nbt_ig_create_map", C.c_int, _vp, _vp, C.c_int, C.c_int, C.c_int, C.c_floa
      C.POINTER(C.c_float), C.POINTER(ClassifyT), _vp, C.POINTER(_vp))
 _sig("nbt_ig_destroy_map", None, _vp)
 _sig("nbt_ig_update_map", C.c_int, _vp, _vp, _vp)
+_sig("nbt_ig_insert_default_params", InsertParamsT)
+_sig("nbt_ig_insert_workspace_words", C.c_uint64, _vp)
+_sig("nbt_ig_insert_scans", C.c_int, _vp, C.POINTER(CameraT), _vp, _vp, _u32, C.POINTER(InsertParamsT),
+     _vp, _vp, _vp, C.c_uint64, _vp)
 _sig("nbt_ig_map_check", C.c_int, _vp, _vp)
 _sig("nbt_ig_map_info", C.c_int, _vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
      C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_size_t))
@@ -325,6 +333,42 @@ def eval_viewpoints(m: Map, cam, poses, ig_out=None, steps_out=None, stream=None
                                        _dev_ptr(ig_out, torch.float32, "ig_out"),
                                        _dev_ptr(steps_out, torch.int64, "steps_out"), _stream(stream)))
     return ig_out, steps_out
+
+
+def insert_default_params():
+    """(l_hit, l_miss, l_min, l_max) the library uses when none are given."""
+    p = _lib.nbt_ig_insert_default_params()
+    return (p.l_hit, p.l_miss, p.l_min, p.l_max)
+
+
+def insert_scans(m: Map, cam, poses, depth, logodds, params=None, prob_out=None, workspace=None, stream=None):
+    """Depth-image insertion into the log-odds grid ``logodds`` (device float32 [nz, ny, nx],
+    updated in place): poses float32 [K, 12], depth float32 [K, H, W] z-depths in metres.
+    ``params`` = (l_hit, l_miss, l_min, l_max) or None for the library's defaults.  ``prob_out``
+    (device float32 like logodds) receives 1/(1+exp(-L)).  Without ``workspace`` the map keeps
+    a zeroed one of its own.  Returns logodds."""
+    torch = _torch()
+    nx, ny, nz = m.dims
+    if tuple(logodds.shape) != (nz, ny, nx):
+        raise ValueError("logodds shape differs from the map")
+    k = int(poses.shape[0])
+    cm = camera(cam)
+    if tuple(depth.shape) != (k, cm.height, cm.width):
+        raise ValueError("depth must be [K, height, width]")
+    words = int(_lib.nbt_ig_insert_workspace_words(m.handle))
+    if workspace is None:
+        workspace = getattr(m, "_insert_ws", None)
+        if workspace is None or workspace.device != logodds.device:
+            workspace = torch.zeros(words, dtype=torch.int32, device=logodds.device)
+            m._insert_ws = workspace
+    prm = None if params is None else C.byref(InsertParamsT(*[float(v) for v in params]))
+    _check(_lib.nbt_ig_insert_scans(m.handle, C.byref(cm), _dev_ptr(poses, torch.float32, "poses"),
+                                    _dev_ptr(depth, torch.float32, "depth"), k, prm,
+                                    _dev_ptr(logodds, torch.float32, "logodds"),
+                                    _dev_ptr(prob_out, torch.float32, "prob_out"),
+                                    _dev_ptr(workspace, torch.int32, "workspace"), int(workspace.numel()),
+                                    _stream(stream)))
+    return logodds
 
 
 def eval_trajectories(m: Map, cam, poses, stream=None, want_visits=True):

@@ -1,0 +1,166 @@
+"""GPU parity of the map update by depth-image insertion against the CPU oracle (C ABI).
+
+Bar: the log-odds grid bit-exact after every call (binary32 adds and clamps in a fixed
+definition); the probabilities within 4 binary32 ulp of the oracle's binary64 logistic; the
+workspace left zero.  End to end: insertion, re-encoding and IG evaluation give the oracle's
+step counts exactly and its IG within 1e-5 relative.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import poses_sphere, scene_spheres
+from workloads.configs import Camera
+from workloads.depth import depth_images
+from workloads.scenes import SceneMap
+
+pytestmark = pytest.mark.gpu
+PARAMS = oracle.DEFAULT_INSERT_PARAMS
+
+
+def _note(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def nbt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2503_22588_amd as nbt
+    return nbt
+
+
+@pytest.fixture(scope="module")
+def ctx(nbt):
+    c = nbt.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def small(nbt, ctx):
+    sc = scene_spheres(n=(40, 36, 44), voxel=0.05, n_spheres=14, seed=901)
+    cam = Camera(37, 23, 60.0, 45.0, 1.5)
+    poses = poses_sphere(sc.poi, 0.7, 6, seed=902)
+    depth = depth_images(sc, cam, poses, invalid_frac=0.05, seed=903)
+    depth[1, 3, 5] = np.nan
+    depth[2, 4, :7] = np.float32(1.5)            # exactly the range: no return
+    depth[2, 5, :7] = np.float32(2.5)            # beyond the range
+    m = nbt.Map(ctx, sc.P, sc.voxel, sc.origin)
+    return sc, cam, poses, depth, m
+
+
+def _ulp_close(a, b, ulps=4):
+    a = np.asarray(a, np.float32)
+    b = np.asarray(b, np.float32)
+    return np.all(np.abs(a.view(np.int32).astype(np.int64) - b.view(np.int32).astype(np.int64)) <= ulps)
+
+
+def test_logodds_bit_exact_from_random_state(nbt, small):
+    import torch
+    sc, cam, poses, depth, m = small
+    _note("insert: random initial log-odds, 6 scans, clamping")
+    rng = np.random.default_rng(904)
+    L0 = rng.uniform(-2.5, 4.0, size=sc.P.shape).astype(np.float32)
+    # the same scans twice in a row, so that clamping is reached from many states
+    P2 = np.concatenate([poses, poses])
+    D2 = np.concatenate([depth, depth])
+    ref = oracle.insert_scans(sc, cam, P2, D2, L0, PARAMS)
+    L = _dev(L0)
+    prob = torch.empty_like(L)
+    nbt.insert_scans(m, cam, _dev(P2), _dev(D2), L, params=PARAMS, prob_out=prob)
+    torch.cuda.synchronize()
+    got = L.cpu().numpy()
+    assert np.array_equal(got.view(np.int32), ref.view(np.int32)), np.argwhere(got != ref)[:5]
+    assert _ulp_close(prob.cpu().numpy(), oracle.logodds_to_prob(ref))
+    assert not m._insert_ws.any()                # the workspace is left zero
+    assert (got == np.float32(PARAMS[3])).any() and (got == np.float32(PARAMS[2])).any()
+
+
+def test_calls_compose_and_default_params(nbt, small):
+    import torch
+    sc, cam, poses, depth, m = small
+    _note("insert: one call per scan, default parameters")
+    L0 = np.zeros(sc.P.shape, np.float32)
+    ref = oracle.insert_scans(sc, cam, poses, depth, L0, PARAMS)
+    L = _dev(L0)
+    dp, dd = _dev(poses), _dev(depth)
+    for k in range(poses.shape[0]):
+        nbt.insert_scans(m, cam, dp[k:k + 1], dd[k:k + 1], L)        # library defaults
+    torch.cuda.synchronize()
+    assert np.array_equal(L.cpu().numpy().view(np.int32), ref.view(np.int32))
+    # no scans: only the probabilities are written
+    prob = torch.full_like(L, -1.0)
+    nbt.insert_scans(m, cam, dp[:0], dd[:0], L, prob_out=prob)
+    torch.cuda.synchronize()
+    assert np.array_equal(L.cpu().numpy(), ref)
+    assert _ulp_close(prob.cpu().numpy(), oracle.logodds_to_prob(ref))
+
+
+def test_argument_errors(nbt, small):
+    import torch
+    sc, cam, poses, depth, m = small
+    L = _dev(np.zeros(sc.P.shape, np.float32))
+    with pytest.raises(nbt.NbtError):
+        nbt.insert_scans(m, cam, _dev(poses), _dev(depth), L, params=(0.8, -0.4, 1.0, -1.0))
+    with pytest.raises(nbt.NbtError):
+        nbt.insert_scans(m, cam, _dev(poses), _dev(depth), L, params=(np.inf, -0.4, -2.0, 3.5))
+    short = torch.zeros(16, dtype=torch.int32, device="cuda")
+    with pytest.raises(nbt.NbtError):
+        nbt.insert_scans(m, cam, _dev(poses), _dev(depth), L, workspace=short)
+    with pytest.raises(ValueError):
+        nbt.insert_scans(m, cam, _dev(poses), _dev(depth[:, :-1]), L)
+    torch.cuda.synchronize()
+    assert not L.cpu().numpy().any()
+
+
+def test_insert_then_evaluate(nbt, ctx, small):
+    """Unknown map (L = 0), scans inserted, map re-encoded from the probabilities, IG evaluated."""
+    import torch
+    sc, cam, poses, depth, m0 = small
+    _note("insert: end to end with IG evaluation")
+    L0 = np.zeros(sc.P.shape, np.float32)
+    ref_L = oracle.insert_scans(sc, cam, poses[:4], depth[:4], L0, PARAMS)
+    ref_P = oracle.logodds_to_prob(ref_L)
+    probe = poses_sphere(sc.poi, 0.6, 10, seed=905)
+    ig_ref, st_ref = oracle.eval_viewpoints(SceneMap(P=ref_P, voxel=sc.voxel, origin=sc.origin, poi=sc.poi),
+                                            cam, probe)
+    m = nbt.Map(ctx, np.full(sc.P.shape, 0.5, np.float32), sc.voxel, sc.origin)
+    L = _dev(L0)
+    P = torch.empty_like(L)
+    nbt.insert_scans(m, cam, _dev(poses[:4]), _dev(depth[:4]), L, params=PARAMS, prob_out=P)
+    m.update(P)
+    ig, st = nbt.eval_viewpoints(m, cam, _dev(probe))
+    torch.cuda.synchronize()
+    m.check()
+    assert np.array_equal(st.cpu().numpy().view(np.uint64), st_ref)
+    rel = np.abs(ig.cpu().numpy() - ig_ref) / np.maximum(np.abs(ig_ref), 1e-30)
+    assert rel.max() <= 1e-5
+    m.close()
+
+
+def test_full_size_two_scans(nbt, ctx):
+    """256^3 at 2 cm, two 640 x 576 scans (the benchmark's image size), whole grid compared."""
+    import torch
+    _note("insert: full size, 2 scans of 640x576")
+    sc = scene_spheres(n=256, voxel=0.02, n_spheres=60, seed=911, r_range=(0.08, 0.4))
+    cam = Camera(640, 576, 75.0, 65.0, 3.0)
+    poses = poses_sphere(sc.poi, 1.2, 2, seed=912)
+    depth = depth_images(sc, cam, poses, invalid_frac=0.02, seed=913)
+    L0 = np.zeros(sc.P.shape, np.float32)
+    ref = oracle.insert_scans(sc, cam, poses, depth, L0, PARAMS)
+    m = nbt.Map(ctx, sc.P, sc.voxel, sc.origin)
+    L = _dev(L0)
+    nbt.insert_scans(m, cam, _dev(poses), _dev(depth), L, params=PARAMS)
+    torch.cuda.synchronize()
+    got = L.cpu().numpy()
+    assert np.array_equal(got.view(np.int32), ref.view(np.int32))
+    assert (got == np.float32(PARAMS[0])).sum() > 1000
+    m.close()
