@@ -153,6 +153,43 @@ def extra_trajectories(nbt, ctx, reps):
                     "includes the box pre-pass and its one host synchronisation"}
 
 
+def extra_insert(nbt, ctx, reps):
+    """Map update: 16 depth scans of 640x576 inserted into a 256^3 log-odds grid (2 cm)."""
+    import numpy as np
+    import torch
+    from workloads import poses_sphere, scene_spheres
+    from workloads.configs import Camera
+    from workloads.depth import depth_images
+    sc = scene_spheres(n=256, voxel=0.02, n_spheres=60, seed=921, r_range=(0.08, 0.4))
+    cam = Camera(640, 576, 75.0, 65.0, 3.0)
+    poses = poses_sphere(sc.poi, 1.2, 16, seed=922)
+    depth = depth_images(sc, cam, poses, invalid_frac=0.02, seed=923)
+    m = nbt.Map(ctx, np.full(sc.P.shape, 0.5, np.float32), sc.voxel, sc.origin)
+    L = torch.zeros(sc.P.shape, dtype=torch.float32, device="cuda")
+    P = torch.empty_like(L)
+    dp, dd = torch.from_numpy(poses).cuda(), torch.from_numpy(depth).cuda()
+    stream = torch.cuda.current_stream()
+    ms_ins = _timed(lambda: nbt.insert_scans(m, cam, dp, dd, L), reps, stream)
+
+    def full():
+        nbt.insert_scans(m, cam, dp, dd, L, prob_out=P)
+        m.update(P)
+
+    ms_full = _timed(full, reps, stream)
+    m.check()
+    rays = poses.shape[0] * cam.width * cam.height
+    measured = int(np.count_nonzero(depth > 0))
+    returns = int(np.count_nonzero((depth > 0) & (depth < cam.range)))
+    m.close()
+    return {"workload": "256^3 log-odds grid (2 cm, 60 spheres), 16 scans of 640x576 z-depth "
+                        "(75x65 deg, 3 m), 2 % dropped pixels",
+            "insert_ms": ms_ins, "scans_per_s": poses.shape[0] / (ms_ins * 1e-3),
+            "rays_per_s": rays / (ms_ins * 1e-3), "measured_pixels": measured, "returns": returns,
+            "update_ms": ms_full,
+            "note": "insert_ms: the 16 scans into the log-odds grid; update_ms adds the probabilities "
+                    "and the re-encoding of the map"}
+
+
 def extra_batch(nbt, ctx, reps):
     """Batched: 64 maps of {64..256}^3, log-uniform 16-2048 perspectives each, one graph launch."""
     import numpy as np
@@ -300,7 +337,7 @@ def main():
                     help="map storage order (default: the library's)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the trajectory and batched measurements")
-    ap.add_argument("--only", choices=("trajectories", "batched", "surrogate"), default=None,
+    ap.add_argument("--only", choices=("trajectories", "batched", "surrogate", "insert"), default=None,
                     help="only run one of the extra workloads (one JSON object)")
     ap.add_argument("--e1-sweep", action="store_true",
                     help="only run the N_P x s_G runtime sweep at 1 cm voxels (one JSON object per line)")
@@ -344,7 +381,8 @@ def main():
         cx = nbt.Context(0)
         run = {"trajectories": lambda: extra_trajectories(nbt, cx, reps=3),
                "batched": lambda: extra_batch(nbt, cx, reps=5),
-               "surrogate": lambda: extra_surrogate(nbt, cx)}[args.only]
+               "surrogate": lambda: extra_surrogate(nbt, cx),
+               "insert": lambda: extra_insert(nbt, cx, reps=5)}[args.only]
         print(json.dumps({args.only: run()}), flush=True)
         return
 
@@ -477,6 +515,8 @@ def main():
         result["batched"] = extra_batch(nbt, cx, reps=5)
         _log("measuring the surrogate (config 5) ...")
         result["surrogate"] = extra_surrogate(nbt, cx)
+        _log("measuring the map update by depth insertion ...")
+        result["insert"] = extra_insert(nbt, cx, reps=5)
     if not args.no_cpu_baseline:
         _log("timing the CPU oracle baseline ...")
         result["cpu_baseline"] = cpu_baseline(scene, cam, poses, args.cpu_seconds)

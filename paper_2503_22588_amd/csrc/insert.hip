@@ -16,9 +16,10 @@
 //   - each voxel marked in the scan moves once: log-odds + l_hit if any ray
 //     hit it, else + l_miss, then clamped to [l_min, l_max] (binary32).
 // Scans are applied in order.  Two passes per scan: a mark pass (one thread
-// per pixel, 2-bit marks ORed atomically into one byte per voxel) and an
-// apply pass (one thread per 4 voxels: it reads their marks, updates the
-// marked log-odds values and clears the marks for the next scan).
+// per pixel, 2-bit marks ORed atomically into one byte per voxel, each OR
+// only when a coherent load finds the bit missing) and an apply pass (one
+// thread per 4 voxels: it reads their marks, updates the marked log-odds
+// values and clears the marks for the next scan).
 #include "host.hpp"
 #include "ray.hpp"
 
@@ -26,8 +27,14 @@ namespace nbt {
 
 constexpr uint32_t kMarkFree = 1u, kMarkHit = 2u;
 
+// Rays of one scan share their first voxels (they leave one camera centre),
+// so most marks are already set: a device-coherent load (served by the L2,
+// never by a stale L1 line) checks the mark and only a missing bit costs an
+// atomic OR.  A load that misses a concurrent OR only adds a redundant one.
 __device__ __forceinline__ void mark_voxel(uint32_t* marks, uint32_t lin, uint32_t bits) {
-    atomicOr(&marks[lin >> 2], bits << ((lin & 3u) * 8u));
+    const uint32_t want = bits << ((lin & 3u) * 8u);
+    const uint32_t cur = __hip_atomic_load(&marks[lin >> 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((cur & want) != want) atomicOr(&marks[lin >> 2], want);
 }
 
 __global__ __launch_bounds__(256) void insert_mark_kernel(DevMap m, CamParams c,
