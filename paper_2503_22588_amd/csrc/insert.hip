@@ -28,19 +28,33 @@ namespace nbt {
 constexpr uint32_t kMarkFree = 1u, kMarkHit = 2u;
 
 // Rays of one scan share their first voxels (they leave one camera centre),
-// so most marks are already set: a device-coherent load (served by the L2,
-// never by a stale L1 line) checks the mark and only a missing bit costs an
-// atomic OR.  A load that misses a concurrent OR only adds a redundant one.
+// so most marks are already set: a load checks the mark and only a missing
+// bit costs an atomic OR.  The load may be served by the L1: every wave
+// starts with an acquire fence, which drops L1 lines cached before this pass
+// (they could show marks that the apply pass has since cleared); lines cached
+// during the pass can only lack bits ORed since, which costs a redundant OR.
+// Rays leaving one camera centre also visit their first voxels in the same
+// steps, so the lanes of a wave that need an OR often need the same one: the
+// first such lane does it for all lanes with the same word and bits (atomics
+// on one address queue at the L2, one per lane).
 __device__ __forceinline__ void mark_voxel(uint32_t* marks, uint32_t lin, uint32_t bits) {
+    const uint32_t w = lin >> 2;
     const uint32_t want = bits << ((lin & 3u) * 8u);
-    const uint32_t cur = __hip_atomic_load(&marks[lin >> 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((cur & want) != want) atomicOr(&marks[lin >> 2], want);
+    const uint32_t cur = marks[w];
+    if ((cur & want) != want) {
+        const uint32_t lane = __lane_id();
+        const uint32_t lw = __builtin_amdgcn_readfirstlane(w);
+        const uint32_t lb = __builtin_amdgcn_readfirstlane(want);
+        const uint32_t ll = __builtin_amdgcn_readfirstlane(lane);
+        if (w != lw || want != lb || lane == ll) atomicOr(&marks[w], want);
+    }
 }
 
 __global__ __launch_bounds__(256) void insert_mark_kernel(DevMap m, CamParams c,
                                                           const float* __restrict__ pose_in,
                                                           const float* __restrict__ depth,
                                                           uint32_t* __restrict__ marks) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (uint32_t)c.W * (uint32_t)c.H) return;
     const int i = (int)(k % (uint32_t)c.W), j = (int)(k / (uint32_t)c.W);
