@@ -16,10 +16,10 @@
 //   - each voxel marked in the scan moves once: log-odds + l_hit if any ray
 //     hit it, else + l_miss, then clamped to [l_min, l_max] (binary32).
 // Scans are applied in order.  Two passes per scan: a mark pass (one thread
-// per pixel, 2-bit marks ORed atomically into one byte per voxel, each OR
-// only when a coherent load finds the bit missing) and an apply pass (one
-// thread per 4 voxels: it reads their marks, updates the marked log-odds
-// values and clears the marks for the next scan).
+// per pixel, 2-bit marks ORed atomically into one byte per voxel, an OR only
+// where a load finds the bit missing, one per wave for lanes that need the
+// same one) and an apply pass (one thread per 4 voxels: it reads their marks,
+// updates the marked log-odds values and clears the marks for the next scan).
 #include "host.hpp"
 #include "ray.hpp"
 
