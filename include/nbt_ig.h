@@ -180,7 +180,7 @@ typedef struct {
 nbt_ig_insert_params nbt_ig_insert_default_params(void);
 
 /* 32-bit words of the device workspace nbt_ig_insert_scans needs for `map`
- * (one mark byte per voxel); 0 for NULL. */
+ * (two mark bytes per voxel); 0 for NULL. */
 uint64_t nbt_ig_insert_workspace_words(const nbt_ig_map* map);
 
 /* Inserts n_scans scans into the log-odds grid of `map`'s geometry.

@@ -16,44 +16,36 @@
 //   - each voxel marked in the scan moves once: log-odds + l_hit if any ray
 //     hit it, else + l_miss, then clamped to [l_min, l_max] (binary32).
 // Scans are applied in order.  Two passes per scan: a mark pass (one thread
-// per pixel, 2-bit marks ORed atomically into one byte per voxel, an OR only
-// where a load finds the bit missing, one per wave for lanes that need the
-// same one) and an apply pass (one thread per 4 voxels: it reads their marks,
-// updates the marked log-odds values and clears the marks for the next scan).
+// per pixel; two mark bytes per voxel, pass and return, each set by a plain
+// store where a load finds it unset) and an apply pass (one thread per 2
+// voxels: it reads their marks, updates the marked log-odds values and
+// clears the marks for the next scan).
 #include "host.hpp"
 #include "ray.hpp"
 
 namespace nbt {
 
-constexpr uint32_t kMarkFree = 1u, kMarkHit = 2u;
+// Two mark bytes per voxel, set by plain byte stores (a byte store touches
+// no neighbouring byte, and any number of rays may store the same 1):
+// byte 2v says a ray passed voxel v, byte 2v + 1 that a ray's return lies in it.
+constexpr uint32_t kMarkFree = 0u, kMarkHit = 1u;
 
 // Rays of one scan share their first voxels (they leave one camera centre),
 // so most marks are already set: a load checks the mark and only a missing
-// bit costs an atomic OR.  The load may be served by the L1: every wave
-// starts with an acquire fence, which drops L1 lines cached before this pass
-// (they could show marks that the apply pass has since cleared); lines cached
-// during the pass can only lack bits ORed since, which costs a redundant OR.
-// Rays leaving one camera centre also visit their first voxels in the same
-// steps, so the lanes of a wave that need an OR often need the same one: the
-// first such lane does it for all lanes with the same word and bits (atomics
-// on one address queue at the L2, one per lane).
-__device__ __forceinline__ void mark_voxel(uint32_t* marks, uint32_t lin, uint32_t bits) {
-    const uint32_t w = lin >> 2;
-    const uint32_t want = bits << ((lin & 3u) * 8u);
-    const uint32_t cur = marks[w];
-    if ((cur & want) != want) {
-        const uint32_t lane = __lane_id();
-        const uint32_t lw = __builtin_amdgcn_readfirstlane(w);
-        const uint32_t lb = __builtin_amdgcn_readfirstlane(want);
-        const uint32_t ll = __builtin_amdgcn_readfirstlane(lane);
-        if (w != lw || want != lb || lane == ll) atomicOr(&marks[w], want);
-    }
+// one costs a store.  The load may be served by the L1: every wave starts
+// with an acquire fence, which drops L1 lines cached before this pass (they
+// could show marks that the apply pass has since cleared); lines cached
+// during the pass can only lack marks stored since, which costs a redundant
+// store.
+__device__ __forceinline__ void mark_voxel(uint8_t* marks, uint32_t lin, uint32_t kind) {
+    uint8_t* p = marks + 2 * (size_t)lin + kind;
+    if (*p == 0) *p = 1;
 }
 
 __global__ __launch_bounds__(256) void insert_mark_kernel(DevMap m, CamParams c,
                                                           const float* __restrict__ pose_in,
                                                           const float* __restrict__ depth,
-                                                          uint32_t* __restrict__ marks) {
+                                                          uint8_t* __restrict__ marks) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (uint32_t)c.W * (uint32_t)c.H) return;
@@ -131,17 +123,18 @@ __global__ __launch_bounds__(256) void insert_mark_kernel(DevMap m, CamParams c,
 __global__ __launch_bounds__(256) void insert_apply_kernel(uint32_t* __restrict__ marks,
                                                            float* __restrict__ L, uint64_t nvox,
                                                            nbt_ig_insert_params p) {
+    // one thread per mark word: two voxels, (pass, return) bytes each
     const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= (nvox + 3) / 4) return;
+    if (w >= (nvox + 1) / 2) return;
     const uint32_t mk = marks[w];
     if (mk == 0u) return;
     marks[w] = 0u;
 #pragma unroll
-    for (uint32_t b = 0; b < 4; ++b) {
-        const uint64_t v = 4 * w + b;
-        const uint32_t f = (mk >> (8u * b)) & 3u;
-        if (f == 0u || v >= nvox) continue;
-        float l = L[v] + ((f & kMarkHit) ? p.l_hit : p.l_miss);
+    for (uint32_t b = 0; b < 2; ++b) {
+        const uint64_t v = 2 * w + b;
+        const uint32_t pass = (mk >> (16u * b)) & 0xFFu, hit = (mk >> (16u * b + 8u)) & 0xFFu;
+        if ((pass | hit) == 0u || v >= nvox) continue;
+        float l = L[v] + (hit ? p.l_hit : p.l_miss);
         l = (p.l_min > l) ? p.l_min : l;
         l = (p.l_max < l) ? p.l_max : l;
         L[v] = l;
@@ -161,7 +154,7 @@ using namespace nbt;
 
 extern "C" uint64_t nbt_ig_insert_workspace_words(const nbt_ig_map* map) {
     if (!map) return 0;
-    return ((uint64_t)map->dm.nx * (uint64_t)map->dm.ny * (uint64_t)map->dm.nz + 3) / 4;
+    return ((uint64_t)map->dm.nx * (uint64_t)map->dm.ny * (uint64_t)map->dm.nz + 1) / 2;
 }
 
 extern "C" nbt_ig_insert_params nbt_ig_insert_default_params(void) {
@@ -192,10 +185,10 @@ extern "C" int nbt_ig_insert_scans(const nbt_ig_map* map, const nbt_ig_camera* c
     if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", map->ctx->device);
     hipStream_t s = (hipStream_t)stream;
     const unsigned mark_blocks = (unsigned)((rays + 255) / 256);
-    const unsigned apply_blocks = (unsigned)(((nvox + 3) / 4 + 255) / 256);
+    const unsigned apply_blocks = (unsigned)(((nvox + 1) / 2 + 255) / 256);
     for (uint32_t k = 0; k < n_scans; ++k) {
         hipLaunchKernelGGL(insert_mark_kernel, dim3(mark_blocks), dim3(256), 0, s, map->dm, c,
-                           poses + 12 * (size_t)k, depth + rays * k, workspace);
+                           poses + 12 * (size_t)k, depth + rays * k, reinterpret_cast<uint8_t*>(workspace));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "insert_mark_kernel");
         hipLaunchKernelGGL(insert_apply_kernel, dim3(apply_blocks), dim3(256), 0, s, workspace, logodds, nvox, p);
