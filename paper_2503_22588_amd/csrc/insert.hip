@@ -17,7 +17,7 @@
 //     hit it, else + l_miss, then clamped to [l_min, l_max] (binary32).
 // Scans are applied in order.  Two passes per scan: a mark pass (one thread
 // per pixel; two mark bytes per voxel, pass and return, each set by a plain
-// store where a load finds it unset) and an apply pass (one thread per 2
+// byte store on every visit) and an apply pass (one thread per 2
 // voxels: it reads their marks, updates the marked log-odds values and
 // clears the marks for the next scan).
 #include "host.hpp"
@@ -30,23 +30,17 @@ namespace nbt {
 // byte 2v says a ray passed voxel v, byte 2v + 1 that a ray's return lies in it.
 constexpr uint32_t kMarkFree = 0u, kMarkHit = 1u;
 
-// Rays of one scan share their first voxels (they leave one camera centre),
-// so most marks are already set: a load checks the mark and only a missing
-// one costs a store.  The load may be served by the L1: every wave starts
-// with an acquire fence, which drops L1 lines cached before this pass (they
-// could show marks that the apply pass has since cleared); lines cached
-// during the pass can only lack marks stored since, which costs a redundant
-// store.
+// Every visit stores its mark.  Checking first (a load, then a store only
+// where the mark is unset) saves stores on the voxels near the camera that
+// all rays pass, but puts a load's latency on every step: slower.
 __device__ __forceinline__ void mark_voxel(uint8_t* marks, uint32_t lin, uint32_t kind) {
-    uint8_t* p = marks + 2 * (size_t)lin + kind;
-    if (*p == 0) *p = 1;
+    marks[2 * (size_t)lin + kind] = 1;
 }
 
 __global__ __launch_bounds__(256) void insert_mark_kernel(DevMap m, CamParams c,
                                                           const float* __restrict__ pose_in,
                                                           const float* __restrict__ depth,
                                                           uint8_t* __restrict__ marks) {
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (uint32_t)c.W * (uint32_t)c.H) return;
     const int i = (int)(k % (uint32_t)c.W), j = (int)(k / (uint32_t)c.W);
