@@ -48,6 +48,19 @@ def test_no_return_within_range_carves_free(d):
     assert out[0, 0].tolist() == [MISS] * 8
 
 
+def test_depth_exactly_at_range_is_no_return():
+    # a 24-voxel row holds the far-plane endpoint (x = 18.5): depth = range carves the row up
+    # to the endpoint's voxel but marks no hit there
+    geom = (1.0, np.zeros(3, np.float32))
+    L = np.zeros((1, 1, 24), np.float32)
+    cam = Camera(1, 1, 0.001, 0.001, 20.0)
+    pose = look_at(np.array([[-1.5, 0.5, 0.5]]), np.array([30.0, 0.5, 0.5]))
+    out = _insert(geom, L, cam, pose, [[[20.0]]])
+    assert out[0, 0].tolist() == [MISS] * 19 + [0] * 5
+    out = _insert(geom, L, cam, pose, [[[19.9]]])              # just inside range: a return
+    assert out[0, 0].tolist() == [MISS] * 18 + [HIT] + [0] * 5
+
+
 @pytest.mark.parametrize("d", [0.0, -1.0, np.nan])
 def test_no_measurement_changes_nothing(d):
     geom, L, cam, pose = _row_setup()
