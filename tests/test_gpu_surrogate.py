@@ -2,9 +2,10 @@
 
 Bar: the patch equals the reference exactly (float32 fractions); trunk
 features and predictions agree with the reference forward that rounds to
-BF16 at the same points within a BF16-derived tolerance (see the design doc:
-max |err| <= 2e-2 * max |reference|); the top-k / final pick equal an exact
-re-ranking of the GPU's own predictions and exact IG.
+BF16 at the same points within a BF16-derived tolerance, max |err| <= 2e-2 *
+max |reference| (a BF16 ulp is 2^-8; a few ulp flips where FP32 accumulation
+lands next to a rounding boundary propagate at that scale); the top-k / final
+pick equal an exact re-ranking of the GPU's own predictions and exact IG.
 """
 
 import numpy as np
