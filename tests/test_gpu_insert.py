@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import poses_sphere, scene_spheres
+from workloads import look_at, poses_sphere, scene_spheres
 from workloads.configs import Camera
 from workloads.depth import depth_images
 from workloads.scenes import SceneMap
@@ -119,6 +119,27 @@ def test_argument_errors(nbt, small):
         nbt.insert_scans(m, cam, _dev(poses), _dev(depth[:, :-1]), L)
     torch.cuda.synchronize()
     assert not L.cpu().numpy().any()
+
+
+def test_hand_placed_rows(nbt, ctx):
+    """Axis-aligned rays along a 24-voxel row (parallel axes, returns on and off voxel faces,
+    depth at and just inside the range, before and beyond the map, no measurement)."""
+    import torch
+    _note("insert: hand-placed rows")
+    P = np.full((1, 1, 24), 0.5, np.float32)
+    origin = np.zeros(3, np.float32)
+    cam = Camera(3, 1, 0.001, 0.001, 20.0)
+    pose = look_at(np.array([[-1.5, 0.5, 0.5]]), np.array([30.0, 0.5, 0.5]))
+    m = nbt.Map(ctx, P, 1.0, origin)
+    depths = [[5.2, 7.9, 5.2], [20.0, 19.9, 1.0], [12.0, 0.0, np.nan], [np.inf, 4.5, 25.0], [-1.0, 2.5, 9.5]]
+    for row in depths:
+        d = np.array(row, np.float32).reshape(1, 1, 3)
+        ref = oracle.insert_scans((1.0, origin), cam, pose, d, np.zeros_like(P), PARAMS)
+        L = _dev(np.zeros_like(P))
+        nbt.insert_scans(m, cam, _dev(pose), _dev(d), L, params=PARAMS)
+        torch.cuda.synchronize()
+        assert np.array_equal(L.cpu().numpy().view(np.int32), ref.view(np.int32)), row
+    m.close()
 
 
 def test_insert_then_evaluate(nbt, ctx, small):
