@@ -45,6 +45,18 @@ def test_host_only_helpers():
     assert e.value.status == b.EINVAL
 
 
+def test_insertion_defaults_are_the_oracles():
+    """The library's default log-odds parameters carry the same binary32 bits as the oracle's
+    (log(p/(1-p)) of 0.7, 0.4, 0.1192, 0.971), and a NULL map needs no workspace."""
+    import numpy as np
+    import oracle
+    import paper_2503_22588_amd as nbt
+    lib = np.array(nbt.insert_default_params(), np.float32)
+    ref = np.array(oracle.DEFAULT_INSERT_PARAMS, np.float32)
+    assert np.array_equal(lib.view(np.int32), ref.view(np.int32))
+    assert nbt.binding._lib.nbt_ig_insert_workspace_words(None) == 0
+
+
 def test_context_creation_reports_missing_device():
     import torch
     if torch.cuda.is_available():
