@@ -346,7 +346,8 @@ def insert_scans(m: Map, cam, poses, depth, logodds, params=None, prob_out=None,
     updated in place): poses float32 [K, 12], depth float32 [K, H, W] z-depths in metres.
     ``params`` = (l_hit, l_miss, l_min, l_max) or None for the library's defaults.  ``prob_out``
     (device float32 like logodds) receives 1/(1+exp(-L)).  Without ``workspace`` the map keeps
-    a zeroed one of its own.  Returns logodds."""
+    a zeroed one of its own; calls that share a workspace must not overlap (one stream, or
+    synchronise between streams).  Returns logodds."""
     torch = _torch()
     nx, ny, nz = m.dims
     if tuple(logodds.shape) != (nz, ny, nx):
