@@ -142,3 +142,22 @@ def test_carved_voxels_are_the_cast_ray_paths_and_hits_hold_the_return_point():
             assert out.ravel()[lin] == HIT, (i, j)
             checked += 1
     assert checked >= 50
+
+
+def test_logodds_to_prob_closed_forms():
+    """The logistic at points where it has an exact rational value: L = 0 -> 1/2,
+    L = +-ln 3 -> 3/4 and 1/4, L = ln(7/3) -> 7/10, L = ln 9 -> 9/10 (each the binary32
+    nearest the rational), the limits for large |L|, and P(L) + P(-L) = 1."""
+    import math
+    pts = {0.0: 0.5, math.log(3.0): 0.75, -math.log(3.0): 0.25, math.log(7.0 / 3.0): 0.7,
+           math.log(9.0): 0.9, -math.log(9.0): 0.1}
+    got = oracle.logodds_to_prob(np.array(list(pts.keys())))
+    assert got.dtype == np.float32
+    assert got.tolist() == [float(np.float32(v)) for v in pts.values()]
+    big = oracle.logodds_to_prob(np.array([100.0, 1e4, -1e4, -100.0]))
+    assert big[0] == 1.0 and big[1] == 1.0 and big[2] == 0.0
+    assert 0.0 < big[3] < 1e-43                         # e^-100 ~ 3.7e-44: a binary32 subnormal
+    L = np.linspace(-12.0, 12.0, 97)
+    s = oracle.logodds_to_prob(L).astype(np.float64) + oracle.logodds_to_prob(-L).astype(np.float64)
+    assert np.all(np.abs(s - 1.0) <= 2.0 ** -24)
+    assert np.all(np.diff(oracle.logodds_to_prob(L).astype(np.float64)) > 0)

@@ -124,3 +124,89 @@ def test_library_blob_writer_matches_reference_layout():
     assert blob == S.pack_weights(params, 3.2, 0.85, 0.26, 41.5)
     got, meta = S.unpack_weights(blob)
     assert np.array_equal(got["fc2.w"], params["fc2.w"].astype(np.float32).astype(np.float64))
+
+
+def _torch_forward_f64(params, meta, patch, poses, poi):
+    """The surrogate's forward pass written with torch's own float64 CPU layers
+    (conv3d with stride 2 and zero padding 1, ReLU, flatten, linear): a second,
+    independent definition of the architecture documented in the blob format."""
+    import torch
+    import torch.nn.functional as F
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
+    x = t(patch)[None]                                      # [1, 2, 32, 32, 32] = (N, C, z, y, x)
+    for k in range(4):
+        x = F.relu(F.conv3d(x, t(params[f"conv{k + 1}.w"]), t(params[f"conv{k + 1}.b"]), stride=2, padding=1))
+    feats = x.reshape(-1)                                   # channel-major, then z, y, x
+    v = t(np.asarray(poses, np.float64).reshape(-1, 12)[:, 9:12]) - t(np.asarray(poi, np.float64))
+    d = torch.linalg.vector_norm(v, dim=1, keepdim=True)
+    inp = torch.cat([feats.expand(v.shape[0], -1), v / d, (d - meta["dist_mean"]) / meta["dist_scale"]], dim=1)
+    h1 = F.relu(F.linear(inp, t(params["fc1.w"]), t(params["fc1.b"])))
+    h2 = F.relu(F.linear(h1, t(params["fc2.w"]), t(params["fc2.b"])))
+    y = F.linear(h2, t(params["fc3.w"])[None], t(params["fc3.b"]))[:, 0]
+    return feats.numpy(), (meta["out_scale"] * y).numpy()
+
+
+def _lively_params(rng):
+    """Random weights scaled per layer so that activations neither die nor explode (about
+    half of every layer's ReLUs active), rounded to float32 as the blob stores them."""
+    params = {}
+    for k, (ci, co) in enumerate(S.LAYERS):
+        fan = ci * 27
+        params[f"conv{k + 1}.w"] = rng.normal(size=(co, ci, 3, 3, 3)) * np.sqrt(2.0 / fan)
+        params[f"conv{k + 1}.b"] = rng.normal(size=co) * 0.05
+    params["fc1.w"] = rng.normal(size=(S.HIDDEN, S.N_IN)) * np.sqrt(2.0 / S.N_IN)
+    params["fc1.b"] = rng.normal(size=S.HIDDEN) * 0.05
+    params["fc2.w"] = rng.normal(size=(S.HIDDEN, S.HIDDEN)) * np.sqrt(2.0 / S.HIDDEN)
+    params["fc2.b"] = rng.normal(size=S.HIDDEN) * 0.05
+    params["fc3.w"] = rng.normal(size=S.HIDDEN) * np.sqrt(1.0 / S.HIDDEN)
+    params["fc3.b"] = rng.normal(size=1) * 0.05
+    return {k: v.astype(np.float32).astype(np.float64) for k, v in params.items()}
+
+
+def test_float64_forward_equals_torch_layers():
+    """predict(emulate_bf16=False) against torch's conv3d / linear in float64 on the CPU: pins
+    the layer chaining, the ReLU after every layer but the last, the flatten order
+    c*8 + z*4 + y*2 + x and the fc1 block that multiplies non-zero trunk features."""
+    rng = np.random.default_rng(21)
+    params = _lively_params(rng)
+    blob = S.pack_weights(params, 3.2, 0.85, 0.26, 41.5)
+    P = rng.choice(np.array([0.2, 0.5, 0.9], np.float32), p=[0.5, 0.4, 0.1], size=(64, 64, 64))
+    poi = np.array([1.63, 1.58, 1.61])
+    poses = np.zeros((300, 12), np.float32)
+    dirs = rng.normal(size=(300, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    poses[:, 9:] = poi + dirs * rng.uniform(0.4, 1.3, size=(300, 1))
+    got = S.predict(blob, P, 0.05, (0, 0, 0), poi, poses, emulate_bf16=False)
+    prm, meta = S.unpack_weights(blob)
+    patch = S.extract_patch(P, 0.05, (0, 0, 0), poi, meta["extent"])
+    feats_ref, ref = _torch_forward_f64(prm, meta, patch, poses, poi)
+    feats = S.trunk(prm, patch, emulate_bf16=False)
+    # the features are alive (not a zero vector that would hide the fc1 block) and varied
+    assert np.count_nonzero(feats_ref) > 100 and np.std(ref) > 1e-3 * np.abs(ref).max()
+    np.testing.assert_allclose(feats, feats_ref, rtol=1e-12, atol=1e-12 * np.abs(feats_ref).max())
+    np.testing.assert_allclose(got, ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
+
+
+def test_float64_forward_flatten_order_is_channel_then_z_y_x():
+    """A single conv4 channel and one fc1 weight per feature position: the prediction reads
+    exactly the feature that torch's flatten puts at c*8 + z*4 + y*2 + x."""
+    rng = np.random.default_rng(22)
+    params = _lively_params(rng)
+    patch = rng.uniform(0.0, 1.0, size=(2, 32, 32, 32))
+    feats = S.trunk(params, patch, emulate_bf16=False).reshape(64, 2, 2, 2)
+    for c, z, y, x in [(0, 0, 0, 1), (3, 1, 0, 0), (17, 0, 1, 0), (63, 1, 1, 1)]:
+        p = {k: v.copy() for k, v in params.items()}
+        p["fc1.w"][:] = 0.0
+        p["fc1.b"][:] = 0.0
+        p["fc1.w"][0, c * 8 + z * 4 + y * 2 + x] = 1.0
+        p["fc2.w"][:] = 0.0
+        p["fc2.b"][:] = 0.0
+        p["fc2.w"][0, 0] = 1.0
+        p["fc3.w"][:] = 0.0
+        p["fc3.w"][0] = 1.0
+        p["fc3.b"][:] = 0.0
+        meta = {"dist_mean": 0.8, "dist_scale": 0.25, "out_scale": 1.0}
+        poses = np.zeros((1, 12))
+        poses[0, 9:] = (1.0, 0.0, 0.0)
+        y_pred = S.head(p, meta, feats.reshape(-1), poses, np.zeros(3), emulate_bf16=False)
+        assert y_pred[0] == max(feats[c, z, y, x], 0.0)
