@@ -235,16 +235,22 @@ int nbt_ig_eval_viewpoints(const nbt_ig_map* map, const nbt_ig_camera* cam, cons
  *   visits[t]      total voxel visits of all its rays (exact; may be NULL: the
  *                  walk then keeps no per-ray visit count, which is faster).
  * Each trajectory's visited set is a bitset over the voxel box holding its
- * frusta, kept in LDS when it fits the context's LDS budget and in global
- * memory otherwise (allocated on demand).  The call synchronises `stream`
- * once (to size the launch).  n_traj == 0 is a no-op.
+ * frusta, kept in LDS; a box with more bits than the context's LDS budget
+ * holds is covered in several passes over the trajectory's rays, each marking
+ * one slice of the box (same results, bit for bit).  Nothing is read back to
+ * the host: the call only enqueues work on `stream` (so it can be captured in
+ * a graph once a call with as many trajectories has sized the workspace).
+ * n_traj == 0 is a no-op.
  */
 int nbt_ig_eval_trajectories(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
                              uint32_t n_traj, uint32_t poses_per_traj, float* ig_union,
                              uint32_t* counts, uint64_t* visits, void* stream);
 
-/* LDS per workgroup that trajectory bitsets may use (0 = the device maximum);
- * larger boxes use global memory.  Context properties (HOST outputs, may be NULL). */
+/* LDS per workgroup that a trajectory bitset may use, its two bookkeeping
+ * words included (0 = the default: as much as does not lower how many union
+ * workgroups fit on a compute unit; capped at the device maximum); larger
+ * boxes take several passes.  Context properties (HOST outputs, may be NULL;
+ * lds_budget reports the bytes in effect for the current workgroup size). */
 int nbt_ig_ctx_set_lds_budget(nbt_ig_ctx* ctx, size_t bytes);
 int nbt_ig_ctx_info(const nbt_ig_ctx* ctx, int* cu_count, size_t* lds_per_group, size_t* lds_budget);
 
@@ -259,6 +265,28 @@ int nbt_ig_ctx_get_traj_waves(const nbt_ig_ctx* ctx, int* waves_per_group);
  */
 int nbt_ig_trace_rays(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
                       uint32_t n, nbt_ig_ray_digest* out, void* stream);
+
+/* Parity mode of the throughput walks: the same kernels as
+ * nbt_ig_eval_viewpoints (in the context's launch shape, pipelined gathers,
+ * incremental offsets in the map's storage order) and nbt_ig_eval_trajectories
+ * (the union walk with its bitset marks), instantiated to also write one
+ * record per ray.  Each record is built from the byte offsets that the walk
+ * gathered, decoded back into voxel coordinates, in visiting order: hash,
+ * steps, stop_lin and reason must equal nbt_ig_trace_rays's; gain is the
+ * gathered words' gains summed in binary64 in visiting order.  The IG, step,
+ * count and visit outputs are those of the untraced calls, bit for bit.
+ *   nbt_ig_trace_viewpoints:   out[p*N_E + k] for pose p, ray k; reserved = 0.
+ *   nbt_ig_trace_trajectories: out[(t*poses_per_traj + l)*N_E + k] for pose l of
+ *                              trajectory t; reserved = the number of visits
+ *                              whose bitset position names another voxel than
+ *                              the one gathered (0 for a correct walk).
+ * Other arguments as for the untraced calls. */
+int nbt_ig_trace_viewpoints(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                            uint32_t n, float* ig_out, uint64_t* steps_out, nbt_ig_ray_digest* out,
+                            void* stream);
+int nbt_ig_trace_trajectories(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                              uint32_t n_traj, uint32_t poses_per_traj, float* ig_union, uint32_t* counts,
+                              uint64_t* visits, nbt_ig_ray_digest* out, void* stream);
 
 /* Full voxel sequences of selected rays.  rays: uint32 [count][2] = (pose
  * index, ray index k); lin_out: int32 [count][max_len] receives the visited

@@ -98,6 +98,8 @@ _sig("nbt_ig_autotune_map", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _v
      C.POINTER(C.c_int), C.POINTER(C.c_float))
 _sig("nbt_ig_ctx_get_traj_waves", C.c_int, _vp, C.POINTER(C.c_int))
 _sig("nbt_ig_trace_rays", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp)
+_sig("nbt_ig_trace_viewpoints", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp, _vp, _vp)
+_sig("nbt_ig_trace_trajectories", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _u32, _vp, _vp, _vp, _vp, _vp)
 _sig("nbt_ig_trace_paths", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _u32, _u32, _vp, _vp, _vp)
 _sig("nbt_ig_ctx_set_launch", C.c_int, _vp, C.POINTER(LaunchT))
 _sig("nbt_ig_ctx_get_launch", C.c_int, _vp, C.POINTER(LaunchT))
@@ -388,8 +390,21 @@ def eval_trajectories(m: Map, cam, poses, stream=None, want_visits=True):
     return ig, counts, visits
 
 
+def _records(out, shape):
+    """nbt_ig_ray_digest records (int32 [R, 8]) as a dict of tensors shaped `shape`."""
+    torch = _torch()
+    return {
+        "hash": out[:, 0:2].contiguous().view(torch.int64).view(*shape),
+        "gain": out[:, 2:4].contiguous().view(torch.float64).view(*shape),
+        "steps": out[:, 4].view(*shape),
+        "stop_lin": out[:, 5].view(*shape),
+        "reason": out[:, 6].view(*shape),
+        "reserved": out[:, 7].view(*shape),
+    }
+
+
 def trace_rays(m: Map, cam, poses, out=None, stream=None):
-    """Per-ray records as a dict of tensors shaped [N, W*H]."""
+    """Per-ray records of the reference walk as a dict of tensors shaped [N, W*H]."""
     torch = _torch()
     cm = camera(cam)
     n = poses.shape[0]
@@ -398,13 +413,43 @@ def trace_rays(m: Map, cam, poses, out=None, stream=None):
         out = torch.empty((n * rays, 8), dtype=torch.int32, device=poses.device)
     _check(_lib.nbt_ig_trace_rays(m.handle, C.byref(cm), _dev_ptr(poses, torch.float32, "poses"), n,
                                   _dev_ptr(out, torch.int32, "out"), _stream(stream)))
-    return {
-        "hash": out[:, 0:2].contiguous().view(torch.int64).view(n, rays),
-        "gain": out[:, 2:4].contiguous().view(torch.float64).view(n, rays),
-        "steps": out[:, 4].view(n, rays),
-        "stop_lin": out[:, 5].view(n, rays),
-        "reason": out[:, 6].view(n, rays),
-    }
+    return _records(out, (n, rays))
+
+
+def trace_viewpoints(m: Map, cam, poses, want_steps=True, stream=None):
+    """The timed per-perspective kernel in its parity instance: (ig [N], steps [N] or None,
+    records dict of tensors shaped [N, W*H])."""
+    torch = _torch()
+    cm = camera(cam)
+    n = poses.shape[0]
+    rays = cm.width * cm.height
+    ig = torch.empty(n, dtype=torch.float32, device=poses.device)
+    steps = torch.empty(n, dtype=torch.int64, device=poses.device) if want_steps else None
+    out = torch.empty((n * rays, 8), dtype=torch.int32, device=poses.device)
+    _check(_lib.nbt_ig_trace_viewpoints(m.handle, C.byref(cm), _dev_ptr(poses, torch.float32, "poses"), n,
+                                        _dev_ptr(ig, torch.float32, "ig"), _dev_ptr(steps, torch.int64, "steps"),
+                                        _dev_ptr(out, torch.int32, "out"), _stream(stream)))
+    return ig, steps, _records(out, (n, rays))
+
+
+def trace_trajectories(m: Map, cam, poses, want_visits=True, stream=None):
+    """The trajectory union kernel in its parity instance: poses [T, L, 12] -> (ig [T],
+    counts [T, 4], visits [T] or None, records dict of tensors shaped [T, L, W*H]; the
+    record's `reserved` counts visits whose bitset position named another voxel)."""
+    torch = _torch()
+    T, L = int(poses.shape[0]), int(poses.shape[1])
+    cm = camera(cam)
+    rays = cm.width * cm.height
+    dev = poses.device
+    ig = torch.empty(T, dtype=torch.float32, device=dev)
+    counts = torch.empty((T, 4), dtype=torch.int32, device=dev)
+    visits = torch.empty(T, dtype=torch.int64, device=dev) if want_visits else None
+    out = torch.empty((max(T * L * rays, 1), 8), dtype=torch.int32, device=dev)
+    _check(_lib.nbt_ig_trace_trajectories(m.handle, C.byref(cm), _dev_ptr(poses, torch.float32, "poses"), T, L,
+                                          _dev_ptr(ig, torch.float32, "ig"), _dev_ptr(counts, None, "counts"),
+                                          _dev_ptr(visits, None, "visits"), _dev_ptr(out, torch.int32, "out"),
+                                          _stream(stream)))
+    return ig, counts, visits, _records(out[:T * L * rays], (T, L, rays))
 
 
 def trace_paths(m: Map, cam, poses, rays_sel, max_len, stream=None):

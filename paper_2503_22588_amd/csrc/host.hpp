@@ -34,7 +34,17 @@ struct DeviceGuard {
 
 inline bool finite_pos(float x) { return std::isfinite(x) && x > 0.0f; }
 
-int ensure_workspace(nbt_ig_ctx* ctx, size_t slots);
+// Grows *p to `bytes` (when smaller than *cap bytes) in the order of stream s:
+// the new buffer is allocated and the old one released as stream-ordered
+// operations, so no other stream of the process waits.  *async records which
+// allocator owns *p (release_buffer needs it).
+int grow_buffer(void** p, size_t* cap, bool* async, size_t bytes, hipStream_t s, const char* what);
+void release_buffer(void* p, bool async, hipStream_t s);
+
+int ensure_workspace(nbt_ig_ctx* ctx, size_t slots, hipStream_t s);
+// LDS bytes of one trajectory workgroup's bitset (with its two extra words)
+// for the context's current budget and workgroup size.
+size_t traj_lds_bytes(const nbt_ig_ctx* ctx);
 int check_camera(const nbt_ig_camera* cam, CamParams* out);
 int check_map(const nbt_ig_map* map);
 
@@ -48,22 +58,21 @@ struct nbt_ig_ctx {
     char arch[64] = {0};
     std::mutex mu;
     nbt::VpAccum* ws = nullptr;          // per-perspective reduction slots, kept zeroed
-    size_t ws_cap = 0;              // slots allocated
+    size_t ws_bytes = 0;
+    bool ws_async = false;
     nbt::VpLaunch vp_launch{4, 3, 0, 0, 8};  // 4 waves, 8x8 tiles, tiles/wave balanced per camera, no remap, 8 gathers in flight
     size_t lds_max = 0;             // device limit of LDS per workgroup (bytes)
-    size_t lds_budget = 0;          // LDS a trajectory bitset may use (bytes)
+    size_t lds_budget = 0;          // LDS a trajectory bitset may use (bytes); 0 = traj_lds_share
+    size_t traj_lds_share[3] = {0, 0, 0};  // LDS per workgroup that keeps the union kernel's occupancy (4/8/16 waves)
     int traj_waves = 8;             // wavefronts per trajectory workgroup (4, 8, 16)
     int map_layout = NBT_IG_LAYOUT_COLUMN4;  // storage order of maps created next
     // trajectory workspace
     nbt::TrajBox* boxes = nullptr;
-    uint32_t* over_list = nullptr;
-    size_t traj_cap = 0;
-    nbt::TrajMeta* meta = nullptr;       // device
-    nbt::TrajMeta* meta_host = nullptr;  // pinned
-    uint32_t* gbits = nullptr;
-    size_t gbits_words = 0;
+    size_t boxes_bytes = 0;
+    bool boxes_async = false;
     unsigned long long* topk_keep = nullptr;   // top-k selection scratch
-    size_t topk_cap = 0;
+    size_t topk_bytes = 0;
+    bool topk_async = false;
 };
 
 struct nbt_ig_map {

@@ -93,19 +93,12 @@ struct VpLaunch {
     int depth;              // gathers in flight per lane (1, 2, 4, 8)
 };
 
-// Voxel box of one trajectory's frusta and where its visited-voxel bitset lives.
+// Voxel box of one trajectory's frusta (its bitset positions: x fastest).
 struct TrajBox {
     int lx, ly, lz;          // min corner (voxels)
     int ax, ay, az;          // extent (voxels)
     uint32_t nbits;          // ax*ay*az, 0 for an empty trajectory
-    uint32_t global;         // 1: bitset in global memory at word offset goff
-    unsigned long long goff;
-};
-
-struct TrajMeta {
-    unsigned int max_bits;           // largest box routed to LDS
-    unsigned int n_global;           // trajectories routed to global memory
-    unsigned long long global_words; // 32-bit words of their bitsets (64-word aligned)
+    uint32_t pad;
 };
 
 // ---- launchers (each defined next to its kernels) ----
@@ -115,9 +108,16 @@ hipError_t launch_encode_map(const float* prob, uint32_t* enc, const DevMap& m, 
 // Copies an encoded map into another storage order (dst laid out as dstm).
 hipError_t launch_relayout(const DevMap& src, uint32_t* dst, const DevMap& dstm, hipStream_t s);
 
+// trace != nullptr: the parity instance of the same kernel, which also writes
+// one record per ray (trace[p * N_E + k]).
 hipError_t launch_eval_viewpoints(const DevMap& m, const CamParams& c, const float* poses,
                                   uint32_t n, float* ig_out, unsigned long long* steps_out,
-                                  VpAccum* ws, const VpLaunch& L, hipStream_t s);
+                                  VpAccum* ws, const VpLaunch& L, hipStream_t s,
+                                  nbt_ig_ray_digest* trace = nullptr);
+
+// Zeroes n per-perspective reduction slots (a fill kernel: no memset node
+// when the caller captures the stream).
+hipError_t launch_clear_slots(VpAccum* ws, uint32_t n, hipStream_t s);
 
 hipError_t launch_trace_rays(const DevMap& m, const CamParams& c, const float* poses, uint32_t n,
                              nbt_ig_ray_digest* out, hipStream_t s);
@@ -127,16 +127,19 @@ hipError_t launch_trace_paths(const DevMap& m, const CamParams& c, const float* 
                               int32_t* lin_out, uint32_t* len_out, hipStream_t s);
 
 hipError_t launch_traj_boxes(const DevMap& m, const CamParams& c, const float* poses, uint32_t T,
-                             uint32_t L, uint32_t budget_bits, TrajBox* boxes, TrajMeta* meta,
-                             uint32_t* over_list, hipStream_t s);
+                             uint32_t L, TrajBox* boxes, hipStream_t s);
 
 // Static LDS of the union kernel (its reductions); the bitset gets the rest.
 size_t traj_static_lds_bytes();
+// The timed union kernel of a workgroup size (4, 8, 16 waves), for occupancy queries.
+const void* traj_union_kernel_ptr(int waves);
 
-hipError_t launch_traj_union(bool global, int waves, const DevMap& m, const CamParams& c,
-                             const float* poses, uint32_t L, uint32_t grid, size_t lds_bytes,
-                             const TrajBox* boxes, const uint32_t* over_list, uint32_t* gbits,
-                             float* ig_union, uint32_t* counts, unsigned long long* visits,
+// One workgroup per trajectory, its bitset in LDS pass_words words at a time
+// (boxes of more bits take several passes); trace != nullptr: the parity
+// instance, one record per ray at trace[(t * L + l) * N_E + k].
+hipError_t launch_traj_union(int waves, const DevMap& m, const CamParams& c, const float* poses, uint32_t L,
+                             uint32_t T, uint32_t pass_words, const TrajBox* boxes, float* ig_union,
+                             uint32_t* counts, unsigned long long* visits, nbt_ig_ray_digest* trace,
                              hipStream_t s);
 
 // Kernel entry points of the persistent batched launch (for graph nodes).

@@ -28,74 +28,70 @@ int hip_fail(hipError_t e, const char* what) {
 
 namespace nbt {
 
-int ensure_workspace(nbt_ig_ctx* ctx, size_t slots) {
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    if (ctx->ws_cap >= slots) return NBT_IG_OK;
-    size_t cap = ctx->ws_cap ? ctx->ws_cap : 1024;
-    while (cap < slots) cap *= 2;
-    if (ctx->ws) {
-        hipError_t e = hipDeviceSynchronize();   // earlier launches may still use the old slots
-        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-        (void)hipFree(ctx->ws);
-        ctx->ws = nullptr;
-        ctx->ws_cap = 0;
+int grow_buffer(void** p, size_t* cap, bool* async, size_t bytes, hipStream_t s, const char* what) {
+    if (*cap >= bytes) return NBT_IG_OK;
+    void* q = nullptr;
+    bool as = true;
+    hipError_t e = hipMallocAsync(&q, bytes, s);
+    if (e == hipErrorNotSupported) {
+        // no stream-ordered allocator: wait for this stream only, then allocate
+        (void)hipGetLastError();
+        as = false;
+        e = hipStreamSynchronize(s);
+        if (e == hipSuccess) e = hipMalloc(&q, bytes);
     }
-    VpAccum* p = nullptr;
-    hipError_t e = hipMalloc(&p, cap * sizeof(VpAccum));
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
-    e = hipMemset(p, 0, cap * sizeof(VpAccum));
-    if (e != hipSuccess) {
+    if (e != hipSuccess) return hip_fail(e, what);
+    if (*p) release_buffer(*p, *async, s);
+    *p = q;
+    *cap = bytes;
+    *async = as;
+    return NBT_IG_OK;
+}
+
+void release_buffer(void* p, bool async, hipStream_t s) {
+    if (!p) return;
+    if (async) {
+        (void)hipFreeAsync(p, s);
+    } else {
+        (void)hipStreamSynchronize(s);
         (void)hipFree(p);
-        return hip_fail(e, "hipMemset(workspace)");
     }
-    ctx->ws = p;
-    ctx->ws_cap = cap;
+}
+
+int ensure_workspace(nbt_ig_ctx* ctx, size_t slots, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const size_t have = ctx->ws_bytes / sizeof(VpAccum);
+    if (have >= slots) return NBT_IG_OK;
+    size_t cap = have ? have : 1024;
+    while (cap < slots) cap *= 2;
+    if (cap >= (1ull << 32)) return fail(NBT_IG_EUNSUPPORTED, "too many perspectives for the workspace");
+    void* p = ctx->ws;
+    if (int rc = grow_buffer(&p, &ctx->ws_bytes, &ctx->ws_async, cap * sizeof(VpAccum), s, "workspace"))
+        return rc;
+    ctx->ws = static_cast<VpAccum*>(p);
+    const hipError_t e = launch_clear_slots(ctx->ws, (uint32_t)cap, s);   // the kernels keep them zero
+    if (e != hipSuccess) return hip_fail(e, "workspace clear");
     return NBT_IG_OK;
 }
 
-int ensure_traj_workspace(nbt_ig_ctx* ctx, size_t T) {
+static int ensure_traj_workspace(nbt_ig_ctx* ctx, size_t T, hipStream_t s) {
     std::lock_guard<std::mutex> lk(ctx->mu);
-    hipError_t e;
-    if (!ctx->meta) {
-        if ((e = hipMalloc(&ctx->meta, sizeof(TrajMeta))) != hipSuccess) return hip_fail(e, "hipMalloc(meta)");
-        if ((e = hipHostMalloc(&ctx->meta_host, sizeof(TrajMeta))) != hipSuccess)
-            return hip_fail(e, "hipHostMalloc(meta)");
-    }
-    if (ctx->traj_cap >= T) return NBT_IG_OK;
-    size_t cap = ctx->traj_cap ? ctx->traj_cap : 1024;
+    if (ctx->boxes_bytes >= T * sizeof(TrajBox)) return NBT_IG_OK;
+    size_t cap = ctx->boxes_bytes ? ctx->boxes_bytes / sizeof(TrajBox) : 1024;
     while (cap < T) cap *= 2;
-    if (ctx->boxes) {
-        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-        (void)hipFree(ctx->boxes);
-        (void)hipFree(ctx->over_list);
-        ctx->boxes = nullptr;
-        ctx->over_list = nullptr;
-        ctx->traj_cap = 0;
-    }
-    if ((e = hipMalloc(&ctx->boxes, cap * sizeof(TrajBox))) != hipSuccess) return hip_fail(e, "hipMalloc(boxes)");
-    if ((e = hipMalloc(&ctx->over_list, cap * sizeof(uint32_t))) != hipSuccess) {
-        (void)hipFree(ctx->boxes);
-        ctx->boxes = nullptr;
-        return hip_fail(e, "hipMalloc(over_list)");
-    }
-    ctx->traj_cap = cap;
+    void* p = ctx->boxes;
+    if (int rc = grow_buffer(&p, &ctx->boxes_bytes, &ctx->boxes_async, cap * sizeof(TrajBox), s,
+                             "trajectory boxes"))
+        return rc;
+    ctx->boxes = static_cast<TrajBox*>(p);
     return NBT_IG_OK;
 }
 
-int ensure_global_bits(nbt_ig_ctx* ctx, size_t words) {
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    if (ctx->gbits_words >= words) return NBT_IG_OK;
-    hipError_t e;
-    if (ctx->gbits) {
-        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-        (void)hipFree(ctx->gbits);
-        ctx->gbits = nullptr;
-        ctx->gbits_words = 0;
-    }
-    if ((e = hipMalloc(&ctx->gbits, words * sizeof(uint32_t))) != hipSuccess)
-        return hip_fail(e, "hipMalloc(trajectory bitsets)");
-    ctx->gbits_words = words;
-    return NBT_IG_OK;
+size_t traj_lds_bytes(const nbt_ig_ctx* ctx) {
+    const int k = ctx->traj_waves == 4 ? 0 : ctx->traj_waves == 8 ? 1 : 2;
+    size_t b = ctx->lds_budget ? ctx->lds_budget : ctx->traj_lds_share[k];
+    if (b > ctx->lds_max) b = ctx->lds_max;
+    return b < 12 ? 12 : b / 4 * 4;      // at least one word of bitset
 }
 
 int check_camera(const nbt_ig_camera* cam, CamParams* out) {
@@ -205,7 +201,36 @@ int nbt_ig_ctx_create(int device, nbt_ig_ctx** out) {
         if (lds > 160 * 1024) lds = 160 * 1024;
         const size_t fixed = traj_static_lds_bytes();
         ctx->lds_max = lds > fixed + 256 ? (lds - fixed - 256) / 256 * 256 : 0;
-        ctx->lds_budget = ctx->lds_max;
+        ctx->lds_budget = 0;
+        // The LDS a union workgroup may take without lowering the number of
+        // its workgroups that registers allow on one CU.
+        size_t per_cu = prop.maxSharedMemoryPerMultiProcessor;
+        if (per_cu == 0 || per_cu > 160 * 1024) per_cu = 160 * 1024;
+        const int waves[3] = {4, 8, 16};
+        for (int k = 0; k < 3; ++k) {
+            int blocks = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, traj_union_kernel_ptr(waves[k]),
+                                                             waves[k] * 64, 0) != hipSuccess || blocks < 1) {
+                (void)hipGetLastError();
+                blocks = 32 / waves[k];
+            }
+            size_t share = per_cu / (size_t)blocks;
+            share = share > fixed + 1024 ? (share - fixed - 512) / 1024 * 1024 : 4096;
+            ctx->traj_lds_share[k] = std::min(share, ctx->lds_max);
+        }
+        // Workspaces sized for common calls up front (larger calls grow them,
+        // stream-ordered).
+        e = hipMalloc(&ctx->ws, 65536 * sizeof(VpAccum));
+        if (e == hipSuccess) e = hipMemset(ctx->ws, 0, 65536 * sizeof(VpAccum));
+        if (e == hipSuccess) ctx->ws_bytes = 65536 * sizeof(VpAccum);
+        if (e == hipSuccess) e = hipMalloc(&ctx->boxes, 16384 * sizeof(TrajBox));
+        if (e == hipSuccess) ctx->boxes_bytes = 16384 * sizeof(TrajBox);
+        if (e != hipSuccess) {
+            if (ctx->ws) (void)hipFree(ctx->ws);
+            if (ctx->boxes) (void)hipFree(ctx->boxes);
+            delete ctx;
+            return hip_fail(e, "context workspace");
+        }
     }
     std::snprintf(ctx->arch, sizeof ctx->arch, "%s", prop.gcnArchName);
     *out = ctx;
@@ -215,13 +240,10 @@ int nbt_ig_ctx_create(int device, nbt_ig_ctx** out) {
 void nbt_ig_ctx_destroy(nbt_ig_ctx* ctx) {
     if (!ctx) return;
     DeviceGuard g(ctx->device);
-    if (ctx->ws) (void)hipFree(ctx->ws);
-    if (ctx->boxes) (void)hipFree(ctx->boxes);
-    if (ctx->over_list) (void)hipFree(ctx->over_list);
-    if (ctx->meta) (void)hipFree(ctx->meta);
-    if (ctx->meta_host) (void)hipHostFree(ctx->meta_host);
-    if (ctx->gbits) (void)hipFree(ctx->gbits);
-    if (ctx->topk_keep) (void)hipFree(ctx->topk_keep);
+    release_buffer(ctx->ws, ctx->ws_async, nullptr);
+    release_buffer(ctx->boxes, ctx->boxes_async, nullptr);
+    release_buffer(ctx->topk_keep, ctx->topk_async, nullptr);
+    if (ctx->ws_async || ctx->boxes_async || ctx->topk_async) (void)hipStreamSynchronize(nullptr);
     delete ctx;
 }
 
@@ -363,8 +385,9 @@ int nbt_ig_map_info(const nbt_ig_map* map, int* nx, int* ny, int* nz, float* vox
     return NBT_IG_OK;
 }
 
-int nbt_ig_eval_viewpoints(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
-                           uint32_t n, float* ig_out, uint64_t* steps_out, void* stream) {
+static int eval_viewpoints_impl(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                                uint32_t n, float* ig_out, uint64_t* steps_out, nbt_ig_ray_digest* trace,
+                                void* stream) {
     if (int rc = check_map(map)) return rc;
     CamParams c;
     if (int rc = check_camera(cam, &c)) return rc;
@@ -373,23 +396,37 @@ int nbt_ig_eval_viewpoints(const nbt_ig_map* map, const nbt_ig_camera* cam, cons
     nbt_ig_ctx* ctx = map->ctx;
     const VpLaunch L = resolve_launch(c, ctx->vp_launch, n, ctx->cu_count);
     const uint64_t groups = vp_groups(c, L);
-    if ((uint64_t)n * groups >= (1ull << 32))
+    if ((uint64_t)n * groups * (uint64_t)(L.waves * 64) >= (1ull << 32))
         return fail(NBT_IG_EUNSUPPORTED, "%u perspectives x %llu workgroups exceed the grid limit", n,
                     (unsigned long long)groups);
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", ctx->device);
+    hipStream_t s = (hipStream_t)stream;
     if (groups > 1)
-        if (int rc = ensure_workspace(ctx, n)) return rc;
+        if (int rc = ensure_workspace(ctx, n, s)) return rc;
     hipError_t e = launch_eval_viewpoints(map->dm, c, poses, n, ig_out,
-                                          reinterpret_cast<unsigned long long*>(steps_out), ctx->ws, L,
-                                          (hipStream_t)stream);
+                                          reinterpret_cast<unsigned long long*>(steps_out), ctx->ws, L, s,
+                                          trace);
     if (e != hipSuccess) return hip_fail(e, "ig_viewpoints_kernel");
     return NBT_IG_OK;
 }
 
-int nbt_ig_eval_trajectories(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
-                             uint32_t n_traj, uint32_t poses_per_traj, float* ig_union,
-                             uint32_t* counts, uint64_t* visits, void* stream) {
+int nbt_ig_eval_viewpoints(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                           uint32_t n, float* ig_out, uint64_t* steps_out, void* stream) {
+    return eval_viewpoints_impl(map, cam, poses, n, ig_out, steps_out, nullptr, stream);
+}
+
+int nbt_ig_trace_viewpoints(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                            uint32_t n, float* ig_out, uint64_t* steps_out, nbt_ig_ray_digest* out,
+                            void* stream) {
+    if (n > 0 && !out) return fail(NBT_IG_EINVAL, "out is NULL");
+    return eval_viewpoints_impl(map, cam, poses, n, ig_out, steps_out, out, stream);
+}
+
+static int eval_trajectories_impl(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                                  uint32_t n_traj, uint32_t poses_per_traj, float* ig_union,
+                                  uint32_t* counts, uint64_t* visits, nbt_ig_ray_digest* trace,
+                                  void* stream) {
     if (int rc = check_map(map)) return rc;
     CamParams c;
     if (int rc = check_camera(cam, &c)) return rc;
@@ -399,43 +436,44 @@ int nbt_ig_eval_trajectories(const nbt_ig_map* map, const nbt_ig_camera* cam, co
     const uint64_t tiles = (uint64_t)((c.W + 7) / 8) * ((c.H + 7) / 8) * poses_per_traj;
     if (tiles >= (1ull << 31)) return fail(NBT_IG_EUNSUPPORTED, "too many rays per trajectory");
     nbt_ig_ctx* ctx = map->ctx;
+    const int waves = ctx->traj_waves;
+    if ((uint64_t)n_traj * (uint64_t)(waves * 64) >= (1ull << 32))
+        return fail(NBT_IG_EUNSUPPORTED, "%u trajectories exceed the grid limit", n_traj);
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", ctx->device);
-    if (int rc = ensure_traj_workspace(ctx, n_traj)) return rc;
     hipStream_t s = (hipStream_t)stream;
-    const uint32_t budget_bits = (uint32_t)std::min<size_t>(ctx->lds_budget * 8, 0xFFFFFFFFull);
-    hipError_t e = hipMemsetAsync(ctx->meta, 0, sizeof(TrajMeta), s);
-    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(meta)");
-    e = launch_traj_boxes(map->dm, c, poses, n_traj, poses_per_traj, budget_bits, ctx->boxes, ctx->meta,
-                          ctx->over_list, s);
+    if (int rc = ensure_traj_workspace(ctx, n_traj, s)) return rc;
+    hipError_t e = launch_traj_boxes(map->dm, c, poses, n_traj, poses_per_traj, ctx->boxes, s);
     if (e != hipSuccess) return hip_fail(e, "traj_box_kernel");
-    e = hipMemcpyAsync(ctx->meta_host, ctx->meta, sizeof(TrajMeta), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "trajectory boxes");
-    const TrajMeta meta = *ctx->meta_host;
-    unsigned long long* vis = reinterpret_cast<unsigned long long*>(visits);
-    if (meta.n_global < n_traj) {
-        const size_t lds = ((size_t)meta.max_bits + 31) / 32 * 4;
-        e = launch_traj_union(false, ctx->traj_waves, map->dm, c, poses, poses_per_traj, n_traj,
-                              lds ? lds : 4, ctx->boxes, ctx->over_list, nullptr, ig_union, counts, vis, s);
-        if (e != hipSuccess)
-            return fail(e == hipErrorOutOfMemory ? NBT_IG_ENOMEM : NBT_IG_EDEVICE,
-                        "traj_union_kernel(lds, %zu bytes of %zu): %s", lds, ctx->lds_max,
-                        hipGetErrorString(e));
-    }
-    if (meta.n_global > 0) {
-        if (int rc = ensure_global_bits(ctx, meta.global_words)) return rc;
-        e = launch_traj_union(true, ctx->traj_waves, map->dm, c, poses, poses_per_traj, meta.n_global, 0,
-                              ctx->boxes, ctx->over_list, ctx->gbits, ig_union, counts, vis, s);
-        if (e != hipSuccess) return hip_fail(e, "traj_union_kernel(global)");
-    }
+    const size_t lds = traj_lds_bytes(ctx);
+    const uint32_t pass_words = (uint32_t)(lds / 4 - 2);
+    e = launch_traj_union(waves, map->dm, c, poses, poses_per_traj, n_traj, pass_words, ctx->boxes, ig_union,
+                          counts, reinterpret_cast<unsigned long long*>(visits), trace, s);
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? NBT_IG_ENOMEM : NBT_IG_EDEVICE,
+                    "traj_union_kernel(%zu bytes of LDS of %zu): %s", lds, ctx->lds_max, hipGetErrorString(e));
     return NBT_IG_OK;
+}
+
+int nbt_ig_eval_trajectories(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                             uint32_t n_traj, uint32_t poses_per_traj, float* ig_union,
+                             uint32_t* counts, uint64_t* visits, void* stream) {
+    return eval_trajectories_impl(map, cam, poses, n_traj, poses_per_traj, ig_union, counts, visits, nullptr,
+                                  stream);
+}
+
+int nbt_ig_trace_trajectories(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                              uint32_t n_traj, uint32_t poses_per_traj, float* ig_union, uint32_t* counts,
+                              uint64_t* visits, nbt_ig_ray_digest* out, void* stream) {
+    if (n_traj > 0 && poses_per_traj > 0 && !out) return fail(NBT_IG_EINVAL, "out is NULL");
+    return eval_trajectories_impl(map, cam, poses, n_traj, poses_per_traj, ig_union, counts, visits, out,
+                                  stream);
 }
 
 int nbt_ig_ctx_set_lds_budget(nbt_ig_ctx* ctx, size_t bytes) {
     if (!ctx) return fail(NBT_IG_EINVAL, "ctx is NULL");
     std::lock_guard<std::mutex> lk(ctx->mu);
-    ctx->lds_budget = (bytes == 0 || bytes > ctx->lds_max) ? ctx->lds_max : bytes;
+    ctx->lds_budget = bytes > ctx->lds_max ? ctx->lds_max : bytes;
     return NBT_IG_OK;
 }
 
@@ -493,7 +531,7 @@ int nbt_ig_ctx_info(const nbt_ig_ctx* ctx, int* cu_count, size_t* lds_per_group,
     if (!ctx) return fail(NBT_IG_EINVAL, "ctx is NULL");
     if (cu_count) *cu_count = ctx->cu_count;
     if (lds_per_group) *lds_per_group = ctx->lds_max;
-    if (lds_budget) *lds_budget = ctx->lds_budget;
+    if (lds_budget) *lds_budget = traj_lds_bytes(ctx);
     return NBT_IG_OK;
 }
 

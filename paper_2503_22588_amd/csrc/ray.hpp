@@ -8,6 +8,8 @@
 // the visited voxel sequence is a deterministic function of the inputs.
 #pragma once
 
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace nbt {
@@ -139,6 +141,93 @@ __device__ __forceinline__ unsigned long long fnv1a_u32(unsigned long long h, ui
 
 constexpr unsigned long long kFnvBasis = 0xcbf29ce484222325ULL;
 
+// Canonical linear index (z*ny + y)*nx + x of the voxel whose word sits at
+// byte offset `off` of the encoded grid, in the map's storage order: the
+// inverse of voxel_offset, written from the layout definitions rather than
+// from the walk's per-axis deltas.  -1 for a border or padding word.
+__device__ __forceinline__ int32_t offset_to_lin(const DevMap& m, uint32_t off) {
+    const uint32_t w = off >> 2;
+    uint32_t X, Y, Z;
+    if (m.tl == 0) {
+        X = w % (uint32_t)m.px;
+        const uint32_t r = w / (uint32_t)m.px;
+        Y = r % (uint32_t)m.py;
+        Z = r / (uint32_t)m.py;
+    } else {
+        const uint32_t t = (uint32_t)m.tl, edge = 1u << t;
+        const uint32_t in_tile = w & (edge * edge - 1u);
+        const uint32_t r = w >> (2u * t);
+        Z = r % (uint32_t)m.pz;
+        const uint32_t tile = r / (uint32_t)m.pz;
+        X = (tile % (uint32_t)m.nbx) * edge + (in_tile & (edge - 1u));
+        Y = (tile / (uint32_t)m.nbx) * edge + (in_tile >> t);
+    }
+    const int x = (int)X - 1, y = (int)Y - 1, z = (int)Z - 1;
+    if (x < 0 || y < 0 || z < 0 || x >= m.nx || y >= m.ny || z >= m.nz) return -1;
+    return (z * m.ny + y) * m.nx + x;
+}
+
+// Parity mode of the throughput walks.  A walk instantiated with WalkTrace
+// keeps, beside each gather in flight, the byte offset it was issued for and
+// whether the generator was still inside the segment; every consumed visit
+// is folded into the record from that offset (decoded by offset_to_lin), so
+// the record shows the voxels the walk actually read, in its order.  Walks
+// instantiated with NoTrace compile to the timed code.
+struct NoTrace {};
+struct WalkTrace {
+    unsigned long long hash = kFnvBasis;   // FNV-1a-64 of the visited linear indices
+    double gain = 0.0;                     // the visited words' gains, binary64 in visiting order
+    uint32_t steps = 0;
+    int32_t last = -1;                     // linear index of the last visit
+    int reason = -1;                       // NBT_IG_RAY_*, -1 while walking
+    uint32_t mismatch = 0;                 // union walk: visits whose bitset position names another voxel
+    uint32_t box_bits = 0;                 // union walk: positions of the trajectory's box
+
+    // slot consumed while the lane is still walking: word x read at `off`,
+    // `live` = the generator had not passed the segment end when it issued it
+    __device__ __forceinline__ void consume(const DevMap& m, uint32_t x, uint32_t off, bool live, float t1) {
+        if (x != kSentinel) {
+            const int32_t lin = offset_to_lin(m, off);
+            hash = fnv1a_u32(hash, (uint32_t)lin);
+            gain += (double)__uint_as_float(x & ~kOccBit);
+            ++steps;
+            last = lin;
+        }
+        if ((int)x < 0)
+            reason = x != kSentinel ? NBT_IG_RAY_HIT
+                   : live ? NBT_IG_RAY_EXIT : (t1 == 1.0f ? NBT_IG_RAY_END : NBT_IG_RAY_EXIT);
+    }
+    // end of the walk: a walk cut by its guard reports EXIT, as the reference walk does
+    __device__ __forceinline__ void finish() {
+        if (reason < 0) reason = NBT_IG_RAY_EXIT;
+    }
+};
+
+template <class TR> constexpr bool traced() { return !std::is_same<TR, NoTrace>::value; }
+
+// The parity record of one ray from its set-up status and walk record.
+__device__ __forceinline__ void write_trace(nbt_ig_ray_digest* out, int status, const WalkTrace& rec) {
+    nbt_ig_ray_digest d;
+    d.hash = kFnvBasis;
+    d.gain = 0.0;
+    d.steps = 0;
+    d.stop_lin = -1;
+    d.reason = NBT_IG_RAY_MISS;
+    d.reserved = 0;
+    if (status == kRayInvalid) {
+        d.reason = NBT_IG_RAY_INVALID;
+        d.gain = __builtin_nan("");
+    } else if (status == kRayOk) {
+        d.hash = rec.hash;
+        d.gain = rec.gain;
+        d.steps = rec.steps;
+        d.stop_lin = rec.last;
+        d.reason = (uint32_t)rec.reason;
+        d.reserved = rec.mismatch;
+    }
+    *out = d;
+}
+
 // Reason a walk stopped (matches NBT_IG_RAY_*).
 enum WalkEnd : int { kEndHit = NBT_IG_RAY_HIT, kEndEnd = NBT_IG_RAY_END, kEndExit = NBT_IG_RAY_EXIT };
 
@@ -146,8 +235,8 @@ enum WalkEnd : int { kEndHit = NBT_IG_RAY_HIT, kEndEnd = NBT_IG_RAY_END, kEndExi
 // added; the walk stops after an Occupied voxel, on the border sentinel (the
 // previous voxel was the last), or when the next face crossing lies beyond
 // the segment end.  The voxel coordinates are kept and addressed through
-// voxel_offset (either layout); when TRACK is set visit(x, y, z) runs for
-// every visited voxel.
+// voxel_offset (either layout); when TRACK is set visit(x, y, z, word) runs
+// for every visited voxel.
 template <bool TRACK, class Visit>
 __device__ __forceinline__ int walk_ray(const DevMap& m, __amdgpu_buffer_rsrc_t rs, RayState& r,
                                         double& acc, uint32_t& steps, Visit&& visit) {
@@ -165,7 +254,7 @@ __device__ __forceinline__ int walk_ray(const DevMap& m, __amdgpu_buffer_rsrc_t 
         acc += (double)g;
         n += sentinel ? 0u : 1u;
         if constexpr (TRACK) {
-            if (!sentinel) visit(r.ix, r.iy, r.iz);
+            if (!sentinel) visit(r.ix, r.iy, r.iz, bits);
         }
         tm = fminf(fminf(tx, ty), tz);
         if ((int)bits < 0 || tm > t1 || n >= guard) break;
@@ -279,9 +368,10 @@ __device__ __forceinline__ void dda_advance(float& tx, float& ty, float& tz, uin
 // consumed (and out-of-range ones read 0).  TL selects the map order (see offset_steps).
 constexpr uint32_t kRunSlots = 8;
 
-template <int P, bool COUNT, int TL>
+template <int P, bool COUNT, int TL, class TR = NoTrace>
 __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buffer_rsrc_t rs,
-                                                   const RayState& r, double& acc, uint32_t& steps) {
+                                                   const RayState& r, double& acc, uint32_t& steps,
+                                                   TR* tr = nullptr) {
     static_assert(P == 2 || P == 4 || P == 8, "pipeline depth");
     const OffsetSteps o = offset_steps<TL>(m, r);
     const float dtx = r.dtx, dty = r.dty, dtz = r.dtz;
@@ -291,12 +381,24 @@ __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buf
     bool alive = true;     // the generator has not yet passed the segment end
 
     uint32_t w[P];
+    // parity mode only: the offset of each gather in flight and whether the
+    // generator was inside the segment when it issued it
+    [[maybe_unused]] uint32_t wo[P];
+    [[maybe_unused]] bool wl[P];
     w[0] = load_word(rs, off);
+    if constexpr (traced<TR>()) {
+        wo[0] = off;
+        wl[0] = true;
+    }
 #pragma unroll
     for (int u = 1; u < P; ++u) {
         dda_advance<TL>(tx, ty, tz, off, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.flip,
                            dtx, dty, dtz);
         w[u] = load_word(rs, off);
+        if constexpr (traced<TR>()) {
+            wo[u] = off;
+            wl[u] = alive;
+        }
     }
     uint32_t n = 0;
     // Every axis index moves one way only, so the border is reached within
@@ -330,10 +432,17 @@ __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buf
             asm volatile("" : "+v"(xs));
             part += fabsf(__uint_as_float(xs));
             if constexpr (COUNT) n += take ? 1u : 0u;
+            if constexpr (traced<TR>()) {
+                if (run) tr->consume(m, x, wo[u], wl[u], t1);
+            }
             run = run && (int)x >= 0;
             dda_advance<TL>(tx, ty, tz, off, alive, t1, o.dx, o.dy, o.dz, o.bigx, o.bigy, o.flip,
                                dtx, dty, dtz);
             w[u] = load_word(rs, off);
+            if constexpr (traced<TR>()) {
+                wo[u] = off;
+                wl[u] = alive;
+            }
         }
         if ((++group & (kRunSlots / P - 1)) == 0u) {
             acc += (double)part;
@@ -343,6 +452,7 @@ __device__ __forceinline__ void walk_ray_pipelined(const DevMap& m, __amdgpu_buf
     }
     acc += (double)part;
     if constexpr (COUNT) steps += n;
+    if constexpr (traced<TR>()) tr->finish();
 }
 
 }  // namespace nbt

@@ -9,6 +9,7 @@
 // fixed point (order independent), the last one writing g_P = sum / N_E
 // (Sec. III, IG calculation: the per-perspective mean of the ray gains).
 #include <tuple>
+#include <type_traits>
 
 #include "ray.hpp"
 #include "reduce.hpp"
@@ -33,14 +34,16 @@ __device__ __forceinline__ uint32_t xcd_logical(uint32_t bid, uint32_t nb, uint3
 // The rays of workgroup-slice g of perspective vp: WAVES waves walk their
 // tiles, then the block's sum is written (groups == 1) or combined with the
 // other slices of the perspective (last slice writes).  Called uniformly by
-// the whole block.
-template <int WAVES, int DEPTH, bool COUNT>
+// the whole block.  TRACE (parity mode) also writes every ray's record to
+// trace[vp * N_E + k], built by the walk below from the offsets it gathers;
+// the walk and the IG arithmetic are those of the timed instance.
+template <int WAVES, int DEPTH, bool COUNT, bool TRACE>
 __device__ __forceinline__ void vp_group(const DevMap& m, const CamParams& c,
                                          const float* __restrict__ pp, uint32_t vp, uint32_t g,
                                          uint32_t groups, uint32_t tiles_x, uint32_t tiles,
                                          int tw_log2, int tpw, float* __restrict__ ig_out,
                                          unsigned long long* __restrict__ steps_out,
-                                         VpAccum* __restrict__ ws) {
+                                         VpAccum* __restrict__ ws, nbt_ig_ray_digest* __restrict__ trace) {
     float pose[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) pose[k] = pp[k];
@@ -64,20 +67,40 @@ __device__ __forceinline__ void vp_group(const DevMap& m, const CamParams& c,
         if (i < c.W && j < c.H) {
             RayState ray;
             const int st = setup_ray(m, c, pose, i, j, ray);
+            [[maybe_unused]] WalkTrace rec;
             if (st == kRayOk) {
                 if constexpr (DEPTH == 1) {
-                    walk_ray<false>(m, rs, ray, acc, steps, [](int, int, int) {});
+                    if constexpr (TRACE) {
+                        // the depth-1 walk addresses each voxel from its coordinates
+                        rec.reason = walk_ray<true>(m, rs, ray, acc, steps, [&](int x, int y, int z, uint32_t word) {
+                            rec.last = (z * m.ny + y) * m.nx + x;
+                            rec.hash = fnv1a_u32(rec.hash, (uint32_t)rec.last);
+                            rec.gain += (double)__uint_as_float(word & ~kOccBit);
+                            ++rec.steps;
+                        });
+                    } else {
+                        walk_ray<false>(m, rs, ray, acc, steps, [](int, int, int, uint32_t) {});
+                    }
                 } else {
+                    auto walk = [&](auto tl) {
+                        constexpr int TLv = decltype(tl)::value;
+                        if constexpr (TRACE)
+                            walk_ray_pipelined<DEPTH, COUNT, TLv, WalkTrace>(m, rs, ray, acc, steps, &rec);
+                        else
+                            walk_ray_pipelined<DEPTH, COUNT, TLv>(m, rs, ray, acc, steps);
+                    };
                     switch (m.tl) {          // the map's order; uniform per workgroup
-                    case 1: walk_ray_pipelined<DEPTH, COUNT, 1>(m, rs, ray, acc, steps); break;
-                    case 2: walk_ray_pipelined<DEPTH, COUNT, 2>(m, rs, ray, acc, steps); break;
-                    case 3: walk_ray_pipelined<DEPTH, COUNT, 3>(m, rs, ray, acc, steps); break;
-                    default: walk_ray_pipelined<DEPTH, COUNT, 0>(m, rs, ray, acc, steps);
+                    case 1: walk(std::integral_constant<int, 1>{}); break;
+                    case 2: walk(std::integral_constant<int, 2>{}); break;
+                    case 3: walk(std::integral_constant<int, 3>{}); break;
+                    default: walk(std::integral_constant<int, 0>{});
                     }
                 }
             } else if (st == kRayInvalid) {
                 invalid = true;
             }
+            if constexpr (TRACE)
+                write_trace(trace + (size_t)vp * ((size_t)c.W * c.H) + (size_t)j * c.W + i, st, rec);
         }
     }
 
@@ -128,16 +151,17 @@ __device__ __forceinline__ void vp_group(const DevMap& m, const CamParams& c,
     }
 }
 
-template <int WAVES, int DEPTH, bool COUNT>
+template <int WAVES, int DEPTH, bool COUNT, bool TRACE>
 __global__ __launch_bounds__(WAVES * 64) void ig_viewpoints_kernel(
     DevMap m, CamParams c, const float* __restrict__ poses, uint32_t groups, uint32_t tiles_x,
     uint32_t tiles, int tw_log2, int tpw, int remap, float* __restrict__ ig_out,
-    unsigned long long* __restrict__ steps_out, VpAccum* __restrict__ ws) {
+    unsigned long long* __restrict__ steps_out, VpAccum* __restrict__ ws,
+    nbt_ig_ray_digest* __restrict__ trace) {
     const uint32_t bid = remap > 0 ? xcd_logical(blockIdx.x, gridDim.x, (uint32_t)remap) : blockIdx.x;
     const uint32_t vp = bid / groups;
     const uint32_t g = bid - vp * groups;
-    vp_group<WAVES, DEPTH, COUNT>(m, c, poses + 12 * (size_t)vp, vp, g, groups, tiles_x, tiles, tw_log2,
-                                  tpw, ig_out, steps_out, ws);
+    vp_group<WAVES, DEPTH, COUNT, TRACE>(m, c, poses + 12 * (size_t)vp, vp, g, groups, tiles_x, tiles,
+                                         tw_log2, tpw, ig_out, steps_out, ws, trace);
 }
 
 // Persistent batched launch: many maps, a CSR of perspectives per map
@@ -179,12 +203,23 @@ __global__ __launch_bounds__(WAVES * 64) void ig_batch_kernel(
         const uint32_t vp = it / groups;
         const uint32_t g = it - vp * groups;
         const DevMap m = maps[s_map];
-        vp_group<WAVES, DEPTH, COUNT>(m, c, poses + 12 * (size_t)vp, vp, g, groups, tiles_x, tiles,
-                                      tw_log2, tpw, ig_out, steps_out, ws);
+        vp_group<WAVES, DEPTH, COUNT, false>(m, c, poses + 12 * (size_t)vp, vp, g, groups, tiles_x, tiles,
+                                             tw_log2, tpw, ig_out, steps_out, ws, nullptr);
     }
 }
 
 __global__ void batch_reset_kernel(unsigned int* queue) { *queue = 0u; }
+
+__global__ __launch_bounds__(256) void clear_slots_kernel(VpAccum* __restrict__ ws, uint32_t n) {
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i < n) ws[i] = VpAccum{0ull, 0ull, 0u, 0u};
+}
+
+hipError_t launch_clear_slots(VpAccum* ws, uint32_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(clear_slots_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ws, n);
+    return hipGetLastError();
+}
 
 // Parity mode: one thread per ray, full record per ray.
 __global__ __launch_bounds__(256) void trace_rays_kernel(DevMap m, CamParams c,
@@ -218,7 +253,7 @@ __global__ __launch_bounds__(256) void trace_rays_kernel(DevMap m, CamParams c,
         double acc = 0.0;
         uint32_t steps = 0;
         const int reason = walk_ray<true>(m, map_rsrc(m), ray, acc, steps,
-                                          [&](int x, int y, int z) {
+                                          [&](int x, int y, int z, uint32_t) {
                                               last = (z * m.ny + y) * m.nx + x;
                                               h = fnv1a_u32(h, (uint32_t)last);
                                           });
@@ -254,7 +289,7 @@ __global__ __launch_bounds__(256) void trace_paths_kernel(DevMap m, CamParams c,
         double acc = 0.0;
         int32_t* dst = lin_out + (size_t)r * max_len;
         uint32_t w = 0;
-        walk_ray<true>(m, map_rsrc(m), ray, acc, steps, [&](int x, int y, int z) {
+        walk_ray<true>(m, map_rsrc(m), ray, acc, steps, [&](int x, int y, int z, uint32_t) {
             if (w < max_len) dst[w] = (z * m.ny + y) * m.nx + x;
             ++w;
         });
@@ -264,7 +299,8 @@ __global__ __launch_bounds__(256) void trace_paths_kernel(DevMap m, CamParams c,
 
 hipError_t launch_eval_viewpoints(const DevMap& m, const CamParams& c, const float* poses,
                                   uint32_t n, float* ig_out, unsigned long long* steps_out,
-                                  VpAccum* ws, const VpLaunch& L0, hipStream_t s) {
+                                  VpAccum* ws, const VpLaunch& L0, hipStream_t s,
+                                  nbt_ig_ray_digest* trace) {
     const VpLaunch L = resolve_launch(c, L0);
     const int tw = 1 << L.tile_w_log2, th = 64 >> L.tile_w_log2;
     const uint32_t tiles_x = (uint32_t)((c.W + tw - 1) / tw);
@@ -272,15 +308,18 @@ hipError_t launch_eval_viewpoints(const DevMap& m, const CamParams& c, const flo
     const uint32_t groups = vp_groups(c, L);
     const dim3 grid((unsigned)((uint64_t)n * groups));
     const auto args = std::make_tuple(m, c, poses, groups, tiles_x, tiles, L.tile_w_log2,
-                                      L.tiles_per_wave, L.xcd_remap, ig_out, steps_out, ws);
+                                      L.tiles_per_wave, L.xcd_remap, ig_out, steps_out, ws, trace);
     auto go = [&](auto kernel, int waves) {
         std::apply([&](auto... a) { hipLaunchKernelGGL(kernel, grid, dim3(waves * 64), 0, s, a...); },
                    args);
     };
     // Without steps_out the walk skips the per-voxel visit count.
     const bool count = steps_out != nullptr;
-#define NBT_VP_GO(W, D) \
-    (count ? go(ig_viewpoints_kernel<W, D, true>, W) : go(ig_viewpoints_kernel<W, D, false>, W))
+#define NBT_VP_GO(W, D)                                                                            \
+    (trace ? (count ? go(ig_viewpoints_kernel<W, D, true, true>, W)                                \
+                    : go(ig_viewpoints_kernel<W, D, false, true>, W))                              \
+           : (count ? go(ig_viewpoints_kernel<W, D, true, false>, W)                               \
+                    : go(ig_viewpoints_kernel<W, D, false, false>, W)))
 #define NBT_VP_DEPTHS(W)                                  \
     case W:                                               \
         switch (L.depth) {                                \

@@ -275,17 +275,11 @@ int nbt_ig_top_k(nbt_ig_ctx* ctx, const float* values, uint32_t n, uint32_t k, u
     const size_t need = topk_scratch_keys(n, k);
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
-        if (ctx->topk_cap < need) {
-            if (ctx->topk_keep) {
-                (void)hipDeviceSynchronize();
-                (void)hipFree(ctx->topk_keep);
-                ctx->topk_keep = nullptr;
-                ctx->topk_cap = 0;
-            }
-            hipError_t e = hipMalloc(&ctx->topk_keep, need * sizeof(unsigned long long));
-            if (e != hipSuccess) return hip_fail(e, "hipMalloc(top-k)");
-            ctx->topk_cap = need;
-        }
+        void* p = ctx->topk_keep;
+        if (int rc = grow_buffer(&p, &ctx->topk_bytes, &ctx->topk_async, need * sizeof(unsigned long long), st,
+                                 "top-k scratch"))
+            return rc;
+        ctx->topk_keep = static_cast<unsigned long long*>(p);
     }
     hipError_t e = launch_topk(values, n, k, ctx->topk_keep, idx_out, st);
     if (e == hipSuccess && val_out) e = launch_gather_values(values, idx_out, k, val_out, st);

@@ -1,7 +1,8 @@
 """GPU parity of the per-trajectory union IG against the CPU oracle (through the C ABI).
 
 Bar: |U|, per-state counts and total visits bit-exact; union IG within 1e-5
-relative.  The LDS and the global-memory bitset paths are both exercised.
+relative.  Boxes that fit the LDS slice in one pass and boxes covered in
+several passes are both exercised.
 """
 
 import math
@@ -97,13 +98,16 @@ def test_small_lds_path(nbt, ctx, small):
     assert np.array_equal(counts.cpu().numpy().astype(np.uint32), got[1])
 
 
-def test_small_global_and_mixed_paths(nbt, ctx, small):
+def test_small_multi_pass(nbt, ctx, small):
     sc, cam, traj, m, ref = small
-    _note("trajectories: global path")
+    _note("trajectories: several LDS passes per box")
+    base = _run(nbt, m, cam, traj)
     try:
-        ctx.set_lds_budget(64)                # every box is larger: all global
-        _check(_run(nbt, m, cam, traj), ref)
-        ctx.set_lds_budget(30 * 1024)         # some fit, some do not
+        ctx.set_lds_budget(64)                # 14 words per pass: every box takes many passes
+        got = _run(nbt, m, cam, traj)
+        _check(got, ref)
+        assert np.array_equal(got[0].view(np.uint32), base[0].view(np.uint32))
+        ctx.set_lds_budget(30 * 1024)         # some boxes fit one pass, some take two
         _check(_run(nbt, m, cam, traj), ref)
         ig, counts, _ = nbt.eval_trajectories(m, cam, _dev(traj), want_visits=False)
         assert np.array_equal(counts.cpu().numpy().astype(np.uint32), ref[1])
@@ -184,7 +188,7 @@ def test_whole_map_boxes(nbt, ctx, shape):
     """Tiny maps seen whole from every pose: each trajectory's box is the whole map, so its
     bitset has nx*ny*nz bits, on and beside multiples of 32 (the last word of an LDS bitset and
     the bit that out-of-box indices are clamped to).  Also the LDS budget at the exact fit of
-    the box, one word under it (global path) and the default."""
+    the box, one word under it (two passes) and the default."""
     nx, ny, nz = shape
     _note(f"trajectories: whole-map boxes {shape}")
     rng = np.random.default_rng(4100 + 97 * nx + 13 * ny + nz)
@@ -213,14 +217,14 @@ def test_whole_map_boxes(nbt, ctx, shape):
 
 def test_cfg4_full_size_sampled(nbt, ctx):
     """Config 4 at its real size (4096 trajectories x 24 poses x 128x96 rays on a 256^3 map):
-    all trajectories on the GPU, the oracle on a seeded sample."""
+    all trajectories on the GPU, the oracle on 8 seeded trajectories."""
     w = make_config(4)
     sc, cam, traj = w.maps[0], w.camera, w.poses[0]
     _note(f"cfg4 full size: {traj.shape}")
     m = nbt.Map(ctx, sc.P, sc.voxel, sc.origin)
     ig, counts, visits = _run(nbt, m, cam, traj)
     rng = np.random.default_rng(44)
-    pick = np.sort(rng.choice(traj.shape[0], size=2, replace=False))
+    pick = np.sort(rng.choice(traj.shape[0], size=8, replace=False))
     ref = oracle.eval_trajectories(sc, cam, traj[pick])
     _check((ig[pick], counts[pick], visits[pick]), ref)
     assert np.all(counts[:, 0] == counts[:, 1:].sum(axis=1))
