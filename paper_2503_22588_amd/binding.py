@@ -354,6 +354,8 @@ def insert_scans(m: Map, cam, poses, depth, logodds, params=None, prob_out=None,
     nx, ny, nz = m.dims
     if tuple(logodds.shape) != (nz, ny, nx):
         raise ValueError("logodds shape differs from the map")
+    if poses.dim() != 2 or int(poses.shape[1]) != 12:
+        raise ValueError("poses must be [K, 12] (row-major camera-to-world rotation, then the centre)")
     k = int(poses.shape[0])
     cm = camera(cam)
     if tuple(depth.shape) != (k, cm.height, cm.width):
@@ -364,6 +366,11 @@ def insert_scans(m: Map, cam, poses, depth, logodds, params=None, prob_out=None,
         if workspace is None or workspace.device != logodds.device:
             workspace = torch.zeros(words, dtype=torch.int32, device=logodds.device)
             m._insert_ws = workspace
+            if stream is not None and not isinstance(stream, int):
+                # the zero fill ran on torch's current stream; the kernels run on `stream`
+                stream.wait_stream(torch.cuda.current_stream(logodds.device))
+            elif isinstance(stream, int):
+                torch.cuda.current_stream(logodds.device).synchronize()
     prm = None if params is None else C.byref(InsertParamsT(*[float(v) for v in params]))
     _check(_lib.nbt_ig_insert_scans(m.handle, C.byref(cm), _dev_ptr(poses, torch.float32, "poses"),
                                     _dev_ptr(depth, torch.float32, "depth"), k, prm,

@@ -121,6 +121,27 @@ def test_argument_errors(nbt, small):
     assert not L.cpu().numpy().any()
 
 
+def test_first_call_on_a_side_stream(nbt, ctx, small):
+    """The map's own workspace is zero-filled on torch's current stream; a first call on
+    another stream must still see it zero.  Poses in any shape but [K, 12] are refused."""
+    import torch
+    sc, cam, poses, depth, _ = small
+    _note("insert: first call on a side stream")
+    m = nbt.Map(ctx, sc.P, sc.voxel, sc.origin)            # fresh map: no workspace yet
+    L0 = np.zeros(sc.P.shape, np.float32)
+    ref = oracle.insert_scans(sc, cam, poses, depth, L0, PARAMS)
+    L, dp, dd = _dev(L0), _dev(poses), _dev(depth)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    nbt.insert_scans(m, cam, dp, dd, L, params=PARAMS, stream=side)
+    side.synchronize()
+    assert np.array_equal(L.cpu().numpy().view(np.int32), ref.view(np.int32))
+    p44 = torch.zeros((poses.shape[0], 4, 4), dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        nbt.insert_scans(m, cam, p44, dd, L)
+    m.close()
+
+
 def test_hand_placed_rows(nbt, ctx):
     """Axis-aligned rays along a 24-voxel row (parallel axes, returns on and off voxel faces,
     depth at and just inside the range, before and beyond the map, no measurement)."""
