@@ -224,6 +224,24 @@ int nbt_ig_map_set_layout(nbt_ig_map* map, int layout, void* stream);
 int nbt_ig_eval_viewpoints(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
                            uint32_t n, float* ig_out, uint64_t* steps_out, void* stream);
 
+/* ---- per-perspective IG without allocation ---------------------------------------
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same results as
+ * nbt_ig_eval_viewpoints, bit for bit, from the same kernels, but the
+ * cross-workgroup reduction slots live in a fixed array of
+ * NBT_IG_NOALLOC_MAX_VIEWPOINTS slots (24 B each, 1.5 MiB) that the library
+ * holds on every device it runs on until the process ends; the call allocates
+ * nothing and never grows a workspace.  n > NBT_IG_NOALLOC_MAX_VIEWPOINTS
+ * returns NBT_IG_EUNSUPPORTED before anything is launched.  The slots needed
+ * are cleared on `stream` by a fill kernel at the start of each call.  All
+ * calls on one device share that array: two such calls that overlap (on
+ * different streams, or from different threads without ordering) race and
+ * give wrong results.  Arguments, layouts and errors as nbt_ig_eval_viewpoints.
+ */
+#define NBT_IG_NOALLOC_MAX_VIEWPOINTS 65536u
+int nbt_ig_eval_viewpoints_noalloc(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                                   uint32_t n, float* ig_out, uint64_t* steps_out, void* stream);
+
 /* ---- per-trajectory IG ----------------------------------------------------------
  * A trajectory is poses_per_traj consecutive poses: poses is float32
  * [n_traj][poses_per_traj][12].  U_t = the set of voxels visited by any ray

@@ -86,6 +86,7 @@ _sig("nbt_ig_map_check", C.c_int, _vp, _vp)
 _sig("nbt_ig_map_info", C.c_int, _vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
      C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_size_t))
 _sig("nbt_ig_eval_viewpoints", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp, _vp)
+_sig("nbt_ig_eval_viewpoints_noalloc", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp, _vp)
 _sig("nbt_ig_eval_trajectories", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _u32, _vp, _vp, _vp, _vp)
 _sig("nbt_ig_ctx_set_lds_budget", C.c_int, _vp, C.c_size_t)
 _sig("nbt_ig_ctx_info", C.c_int, _vp, C.POINTER(C.c_int), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t))
@@ -334,6 +335,21 @@ def eval_viewpoints(m: Map, cam, poses, ig_out=None, steps_out=None, stream=None
     _check(_lib.nbt_ig_eval_viewpoints(m.handle, C.byref(cm), _dev_ptr(poses, torch.float32, "poses"), n,
                                        _dev_ptr(ig_out, torch.float32, "ig_out"),
                                        _dev_ptr(steps_out, torch.int64, "steps_out"), _stream(stream)))
+    return ig_out, steps_out
+
+
+NOALLOC_MAX_VIEWPOINTS = 65536
+
+
+def eval_viewpoints_noalloc(m: Map, cam, poses, ig_out, steps_out=None, stream=None):
+    """nbt_ig_eval_viewpoints_noalloc: as eval_viewpoints, into caller-given outputs, with the
+    library's fixed reduction slots (at most NOALLOC_MAX_VIEWPOINTS perspectives; calls that
+    overlap on one device race)."""
+    torch = _torch()
+    cm = camera(cam)
+    _check(_lib.nbt_ig_eval_viewpoints_noalloc(m.handle, C.byref(cm), _dev_ptr(poses, torch.float32, "poses"),
+                                               int(poses.shape[0]), _dev_ptr(ig_out, torch.float32, "ig_out"),
+                                               _dev_ptr(steps_out, torch.int64, "steps_out"), _stream(stream)))
     return ig_out, steps_out
 
 

@@ -5,6 +5,33 @@ using namespace nbt;
 
 namespace {
 thread_local std::string g_last_error = "no error";
+
+// Reduction slots of nbt_ig_eval_viewpoints_noalloc: one file-scope array that
+// every device holds in its own memory for the life of the process.  Host code
+// never passes the array's name to a kernel (on the host it only stands in for
+// the symbol): the device address of each device's copy is looked up once, with
+// that device current, and kept in g_scratch_dev.
+constexpr uint32_t kNoAllocSlots = NBT_IG_NOALLOC_MAX_VIEWPOINTS;
+constexpr int kNoAllocDevices = 64;
+static __device__ __align__(256) nbt::VpAccum scratch[kNoAllocSlots];
+std::mutex g_scratch_mu;
+nbt::VpAccum* g_scratch_dev[kNoAllocDevices] = {};
+
+// Called from nbt_ig_ctx_create with `device` current.
+int init_noalloc_scratch(int device) {
+    if (device >= kNoAllocDevices) return NBT_IG_OK;       // the entry point refuses such devices
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[device]) return NBT_IG_OK;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return nbt::hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                      "address of the no-allocation scratch");
+    e = nbt::launch_clear_slots(static_cast<nbt::VpAccum*>(ptr), kNoAllocSlots, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) return nbt::hip_fail(e, "clearing the no-allocation scratch");
+    g_scratch_dev[device] = static_cast<nbt::VpAccum*>(ptr);
+    return NBT_IG_OK;
+}
 }  // namespace
 
 namespace nbt {
@@ -231,6 +258,12 @@ int nbt_ig_ctx_create(int device, nbt_ig_ctx** out) {
             delete ctx;
             return hip_fail(e, "context workspace");
         }
+        if (int rc = init_noalloc_scratch(device)) {
+            (void)hipFree(ctx->ws);
+            (void)hipFree(ctx->boxes);
+            delete ctx;
+            return rc;
+        }
     }
     std::snprintf(ctx->arch, sizeof ctx->arch, "%s", prop.gcnArchName);
     *out = ctx;
@@ -387,7 +420,7 @@ int nbt_ig_map_info(const nbt_ig_map* map, int* nx, int* ny, int* nz, float* vox
 
 static int eval_viewpoints_impl(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
                                 uint32_t n, float* ig_out, uint64_t* steps_out, nbt_ig_ray_digest* trace,
-                                void* stream) {
+                                void* stream, bool noalloc = false) {
     if (int rc = check_map(map)) return rc;
     CamParams c;
     if (int rc = check_camera(cam, &c)) return rc;
@@ -402,11 +435,25 @@ static int eval_viewpoints_impl(const nbt_ig_map* map, const nbt_ig_camera* cam,
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", ctx->device);
     hipStream_t s = (hipStream_t)stream;
-    if (groups > 1)
+    VpAccum* ws = ctx->ws;
+    if (noalloc) {
+        if (n > kNoAllocSlots)
+            return fail(NBT_IG_EUNSUPPORTED, "%u perspectives exceed the %u slots of the no-allocation variant", n,
+                        kNoAllocSlots);
+        if (ctx->device >= kNoAllocDevices || !g_scratch_dev[ctx->device])
+            return fail(NBT_IG_EUNSUPPORTED, "device %d has no no-allocation scratch", ctx->device);
+        ws = g_scratch_dev[ctx->device];
+        if (groups > 1) {
+            // the slots start at zero whatever an earlier call on this device left
+            const hipError_t e = launch_clear_slots(ws, n, s);
+            if (e != hipSuccess) return hip_fail(e, "clear_slots_kernel");
+        }
+    } else if (groups > 1) {
         if (int rc = ensure_workspace(ctx, n, s)) return rc;
+        ws = ctx->ws;
+    }
     hipError_t e = launch_eval_viewpoints(map->dm, c, poses, n, ig_out,
-                                          reinterpret_cast<unsigned long long*>(steps_out), ctx->ws, L, s,
-                                          trace);
+                                          reinterpret_cast<unsigned long long*>(steps_out), ws, L, s, trace);
     if (e != hipSuccess) return hip_fail(e, "ig_viewpoints_kernel");
     return NBT_IG_OK;
 }
@@ -414,6 +461,11 @@ static int eval_viewpoints_impl(const nbt_ig_map* map, const nbt_ig_camera* cam,
 int nbt_ig_eval_viewpoints(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
                            uint32_t n, float* ig_out, uint64_t* steps_out, void* stream) {
     return eval_viewpoints_impl(map, cam, poses, n, ig_out, steps_out, nullptr, stream);
+}
+
+int nbt_ig_eval_viewpoints_noalloc(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,
+                                   uint32_t n, float* ig_out, uint64_t* steps_out, void* stream) {
+    return eval_viewpoints_impl(map, cam, poses, n, ig_out, steps_out, nullptr, stream, true);
 }
 
 int nbt_ig_trace_viewpoints(const nbt_ig_map* map, const nbt_ig_camera* cam, const float* poses,

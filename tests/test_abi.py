@@ -81,3 +81,9 @@ def test_binding_constants_match_the_header():
     for required in ("OK", "EINVAL", "RAY_HIT", "RAY_EXIT", "OCCUPIED", "LAYOUT_LINEAR", "LAYOUT_COLUMN4"):
         assert required in values and hasattr(nbt.binding, required), required
     assert checked >= 14
+
+
+def test_noalloc_limit_matches_the_header():
+    import paper_2503_22588_amd as nbt
+    m = re.search(r"#define\s+NBT_IG_NOALLOC_MAX_VIEWPOINTS\s+(\d+)u?", open(HEADER).read())
+    assert m and int(m.group(1)) == nbt.binding.NOALLOC_MAX_VIEWPOINTS
