@@ -80,6 +80,21 @@ def measured_counters():
     return vals
 
 
+def cpu_identity():
+    """The host CPU as lscpu names it, and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model or platform.processor() or platform.machine(),
+            "nproc": os.cpu_count(), "cores_allowed": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(scene, cam, poses, budget_s):
     """The oracle, single-threaded, on a seeded sample of the same perspectives."""
     import numpy as np
@@ -94,6 +109,7 @@ def cpu_baseline(scene, cam, poses, budget_s):
     t0 = time.perf_counter()
     _, steps = oracle.eval_viewpoints(scene, cam, sample)
     dt = time.perf_counter() - t0
+    ident = cpu_identity()
     return {
         "value": k / dt,
         "unit": "viewpoint evals/s",
@@ -101,9 +117,74 @@ def cpu_baseline(scene, cam, poses, budget_s):
         "kind": "oracle",
         "sample": f"{k} of {poses.shape[0]} perspectives (seeded permutation), all "
                   f"{cam.width}x{cam.height} rays each; {int(steps.sum())} voxel steps in {dt:.1f} s "
-                  f"on {platform.processor() or platform.machine()}",
+                  f"on one core of {ident['cpu_model']} ({ident['nproc']} logical CPUs)",
         "voxel_steps_per_s": float(steps.sum()) / dt,
+        **ident,
     }
+
+
+def _oracle_other_workloads(core, conn):
+    """Child process (started before this program touches the GPU), pinned to one core: the
+    oracle on the 64^3 sphere workload and the 64-map batch in full, and on 64 of the 4096
+    trajectories of the trajectory workload."""
+    try:
+        os.sched_setaffinity(0, {core})
+        import numpy as np
+        import oracle
+        from workloads import make_config
+        out = {}
+        w = make_config(1)
+        t0 = time.perf_counter()
+        _, st = oracle.eval_viewpoints(w.maps[0], w.camera, w.poses[0])
+        dt = time.perf_counter() - t0
+        out["plain_64"] = {"workload": "64^3 sphere map, 32 perspectives, 64x48 rays (all)", "seconds": dt,
+                           "viewpoint_evals_per_s": w.poses[0].shape[0] / dt,
+                           "voxel_steps_per_s": float(st.sum()) / dt}
+        w = make_config(3)
+        t0 = time.perf_counter()
+        tot, nv = 0, 0
+        for sc, ps in zip(w.maps, w.poses):
+            _, st = oracle.eval_viewpoints(sc, w.camera, ps)
+            tot += int(st.sum())
+            nv += ps.shape[0]
+        dt = time.perf_counter() - t0
+        out["batched"] = {"workload": f"64 maps, {nv} perspectives, 64x48 rays (all)", "seconds": dt,
+                          "viewpoint_evals_per_s": nv / dt, "voxel_steps_per_s": tot / dt}
+        w = make_config(4)
+        sub = w.poses[0][np.random.default_rng(11).permutation(w.poses[0].shape[0])[:64]]
+        t0 = time.perf_counter()
+        _, _, visits = oracle.eval_trajectories(w.maps[0], w.camera, sub)
+        dt = time.perf_counter() - t0
+        out["trajectories"] = {"workload": "64 of the 4096 trajectories (seeded), 24 poses x 128x96 rays each",
+                               "seconds": dt, "trajectory_evals_per_s": 64 / dt,
+                               "voxel_steps_per_s": float(np.sum(visits)) / dt,
+                               "note": "a subset: the rate per trajectory, not the full 4096"}
+        conn.send(out)
+    except Exception as e:  # reported in the JSON line, never fatal
+        conn.send({"error": f"{type(e).__name__}: {e}"})
+    finally:
+        conn.close()
+
+
+def start_other_baselines():
+    """Starts _oracle_other_workloads on the last allowed core; returns (process, pipe)."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    parent, child = ctx.Pipe(duplex=False)
+    core = max(os.sched_getaffinity(0))
+    p = ctx.Process(target=_oracle_other_workloads, args=(core, child), daemon=True)
+    p.start()
+    child.close()
+    return p, parent
+
+
+def finish_other_baselines(handle, timeout_s=240.0):
+    p, conn = handle
+    res = conn.recv() if conn.poll(timeout_s) else {"error": f"not done within {timeout_s:.0f} s"}
+    p.join(5)
+    if p.is_alive():
+        p.terminate()
+    return res
 
 
 def _timed(fn, reps, stream):
@@ -120,7 +201,61 @@ def _timed(fn, reps, stream):
     return e0.elapsed_time(e1) / reps
 
 
-def extra_trajectories(nbt, ctx, reps):
+CEILING_SIZES = ((1 << 20, "1MiB"), (64 << 20, "64MiB"), (1 << 30, "1GiB"))
+
+
+def measure_ceilings(nbt, ctx, reps=10):
+    """Useful-byte rates of the library's memory probes (nbt_ig_probe_memory) over working sets
+    that fit each XCD's L2 (1 MiB), that only the Infinity Cache holds (64 MiB: above the 8 x
+    4 MiB of L2, within its 256 MiB) and that only HBM holds (1 GiB).  Gathers are 4-byte words
+    at pseudo-random positions, one per lane (`gather`) or one 16-byte piece per quad
+    (`quad_gather`, the coalescing best case of a 2x2 ray quad)."""
+    import torch
+    buf = torch.randint(-2 ** 31, 2 ** 31 - 1, ((1 << 30) // 4,), dtype=torch.int32, device="cuda")
+    sink = nbt.binding.probe_memory(ctx, nbt.binding.PROBE_STREAM, buf[:4], 1)
+    stream = torch.cuda.current_stream()
+    lanes = 256 * 8 * ctx.info()["cu_count"]
+    loads = 1024
+    out = {}
+    for size, label in CEILING_SIZES:
+        b = buf[: size // 4]
+        passes = max(1, (512 << 20) // size)
+        ms = _timed(lambda: nbt.binding.probe_memory(ctx, nbt.binding.PROBE_STREAM, b, passes, sink), reps, stream)
+        row = {"stream_gbs": passes * size / (ms * 1e-3) / 1e9}
+        for name, kind in (("gather", nbt.binding.PROBE_GATHER), ("quad_gather", nbt.binding.PROBE_QUAD_GATHER)):
+            ms = _timed(lambda: nbt.binding.probe_memory(ctx, kind, b, loads, sink), reps, stream)
+            row[f"{name}_words_per_s"] = lanes * loads / (ms * 1e-3)
+            row[f"{name}_gbs"] = 4 * lanes * loads / (ms * 1e-3) / 1e9
+        out[label] = row
+    del buf
+    torch.cuda.empty_cache()
+    return out
+
+
+def level_fractions(steps_per_s, map_bytes, ceilings):
+    """The walk's voxel-step rate (one 4-byte word per step) against the probes' rates at the
+    working set closest to the map's size."""
+    if not ceilings:
+        return None
+    label = "1MiB" if map_bytes <= (4 << 20) else ("64MiB" if map_bytes <= (192 << 20) else "1GiB")
+    c = ceilings[label]
+    level = {"1MiB": "L2", "64MiB": "Infinity Cache (MALL)", "1GiB": "HBM"}[label]
+    return {"map_bytes": map_bytes, "level": level, "ceiling_working_set": label,
+            "frac_vs_stream": 4 * steps_per_s / (c["stream_gbs"] * 1e9),
+            "frac_vs_quad_gather": steps_per_s / c["quad_gather_words_per_s"],
+            "frac_vs_gather": steps_per_s / c["gather_words_per_s"]}
+
+
+def roofline_of(kernel, steps_per_s, map_bytes, ceilings):
+    """The contract's roofline object for a walk kernel: algorithmic bytes (4 per voxel step)
+    against the HBM peak, plus the fractions of the measured ceilings of the map's level."""
+    ach = 4 * steps_per_s / 1e9
+    return {"kernel": kernel, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None,
+            "levels": level_fractions(steps_per_s, map_bytes, ceilings)}
+
+
+def extra_trajectories(nbt, ctx, reps, ceilings=None):
     """Trajectory IG: 256^3 sphere map, 4096 trajectories x 24 poses, 128x96 rays."""
     import numpy as np
     import torch
@@ -150,7 +285,9 @@ def extra_trajectories(nbt, ctx, reps):
             "mean_unique_voxels": float(counts[:, 0].float().mean().item()),
             "map_layout": nbt.LAYOUT_NAMES[layout], "waves_per_group": waves,
             "note": "timed without the visit count (its voxel steps come from one untimed counting call); "
-                    "includes the box pre-pass and its one host synchronisation"}
+                    "includes the box pre-pass; nothing is read back to the host",
+            "roofline": roofline_of("traj_union_kernel", vis / (ms * 1e-3), int(m.info()["device_bytes"]),
+                                    ceilings)}
 
 
 def extra_insert(nbt, ctx, reps):
@@ -190,7 +327,7 @@ def extra_insert(nbt, ctx, reps):
                     "and the re-encoding of the map"}
 
 
-def extra_batch(nbt, ctx, reps):
+def extra_batch(nbt, ctx, reps, ceilings=None):
     """Batched: 64 maps of {64..256}^3, log-uniform 16-2048 perspectives each, one graph launch."""
     import numpy as np
     import torch
@@ -212,7 +349,9 @@ def extra_batch(nbt, ctx, reps):
     res = {"workload": f"64 maps (sizes in {{64,96,128,192,256}}^3, 5 cm), {n} perspectives, 64x48 rays",
            "batch_latency_ms": ms, "viewpoint_evals_per_s": n / (ms * 1e-3), "rays_per_s": rays / (ms * 1e-3),
            "voxel_steps_per_s": steps / (ms * 1e-3), "launch": b.get_launch(),
-           "map_layout": nbt.LAYOUT_NAMES[layout]}
+           "map_layout": nbt.LAYOUT_NAMES[layout],
+           "roofline": roofline_of("ig_batch_kernel", steps / (ms * 1e-3),
+                                   sum(int(mm.info()["device_bytes"]) for mm in maps), ceilings)}
     b.close()
     return res
 
@@ -280,11 +419,13 @@ def extra_surrogate(nbt, ctx, n_maps=16, n_cand=65536, k_rescores=(64, 256, 1024
             "prediction_nmae": float(np.mean(nmae))}
 
 
-def e1_sweep(nbt, ctx, oracle_max_s=60.0):
+def e1_sweep(nbt, ctx, s_gs=(5, 50, 100, 200), n_ps=(100, 250, 500, 750, 1000), oracle_max_s=60.0,
+             oracle_n_ps=None, emit=None):
     """Stand-in for the paper's runtime sweep (Sec. V, online capabilities): N_P perspectives
     sampled in the 1 m ball around the PoI (Eq. 1), endpoint grid spacing s_G * s_Vox,
     s_Vox = 1 cm.  GPU: end-to-end (pose upload, kernels, IG download) and kernel-only;
-    CPU: the single-threaded oracle.  Prints one JSON object per configuration."""
+    CPU: the single-threaded oracle (within oracle_max_s, only for N_P in oracle_n_ps when
+    given).  Returns the rows; emit(row) is called for each as it is measured."""
     import math
     import numpy as np
     import torch
@@ -294,9 +435,10 @@ def e1_sweep(nbt, ctx, oracle_max_s=60.0):
     poi = np.asarray(sc.extra["object_tops"][0], np.float64)
     m = nbt.Map(ctx, sc.P, sc.voxel, sc.origin)
     spent = 0.0
-    for s_g in (5, 50, 100, 200):
+    rows = []
+    for s_g in s_gs:
         cam = nbt.camera_from_grid(math.radians(75.0), math.radians(65.0), 1.5, 0.01, s_g)
-        for n_p in (100, 250, 500, 750, 1000):
+        for n_p in n_ps:
             poses = poses_ball(poi, 1.0, n_p, seed=22588 + 7000 + n_p)
             stream = torch.cuda.current_stream()
             dp = torch.from_numpy(poses).cuda()
@@ -314,14 +456,18 @@ def e1_sweep(nbt, ctx, oracle_max_s=60.0):
             e2e = (time.perf_counter() - t0) * 100.0
             row = {"s_G": s_g, "N_P": n_p, "rays_per_perspective": cam.width * cam.height,
                    "gpu_kernel_ms": kern, "gpu_end_to_end_ms": e2e}
-            if spent < oracle_max_s:
+            if spent < oracle_max_s and (oracle_n_ps is None or n_p in oracle_n_ps):
                 t0 = time.perf_counter()
                 oracle.eval_viewpoints(sc, (cam.width, cam.height, cam.tan_half_fov_h, cam.tan_half_fov_v,
                                             cam.range), poses)
                 dt = time.perf_counter() - t0
                 spent += dt
                 row["cpu_oracle_ms"] = dt * 1e3
-            print(json.dumps(row), flush=True)
+            rows.append(row)
+            if emit:
+                emit(row)
+    m.close()
+    return rows
 
 
 def main():
@@ -337,7 +483,9 @@ def main():
                     help="map storage order (default: the library's)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the trajectory and batched measurements")
-    ap.add_argument("--only", choices=("trajectories", "batched", "surrogate", "insert"), default=None,
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip the memory-probe ceilings (stream, gather) and the fractions against them")
+    ap.add_argument("--only", choices=("trajectories", "batched", "surrogate", "insert", "ceilings"), default=None,
                     help="only run one of the extra workloads (one JSON object)")
     ap.add_argument("--e1-sweep", action="store_true",
                     help="only run the N_P x s_G runtime sweep at 1 cm voxels (one JSON object per line)")
@@ -358,6 +506,12 @@ def main():
         print(kernel_fingerprint())
         return
 
+    # the oracle's other workloads run in a child process on one core while the GPU is
+    # measured (started before anything here touches the GPU)
+    other_cpu = None
+    if not (args.no_cpu_baseline or args.only or args.e1_sweep or args.calibrate_copy):
+        other_cpu = start_other_baselines()
+
     import numpy as np
     import torch
 
@@ -375,14 +529,15 @@ def main():
     from workloads import make_config
 
     if args.e1_sweep:
-        e1_sweep(nbt, nbt.Context(0))
+        e1_sweep(nbt, nbt.Context(0), emit=lambda row: print(json.dumps(row), flush=True))
         return
     if args.only:
         cx = nbt.Context(0)
         run = {"trajectories": lambda: extra_trajectories(nbt, cx, reps=3),
                "batched": lambda: extra_batch(nbt, cx, reps=5),
                "surrogate": lambda: extra_surrogate(nbt, cx),
-               "insert": lambda: extra_insert(nbt, cx, reps=5)}[args.only]
+               "insert": lambda: extra_insert(nbt, cx, reps=5),
+               "ceilings": lambda: measure_ceilings(nbt, cx)}[args.only]
         print(json.dumps({args.only: run()}), flush=True)
         return
 
@@ -430,6 +585,11 @@ def main():
     m.check()
     if not torch.equal(ig, ig_counted):
         raise RuntimeError("IG differs between the counting and the non-counting launch")
+
+    ceilings = None
+    if not args.no_ceilings:
+        _log("measuring the memory ceilings ...")
+        ceilings = measure_ceilings(nbt, ctx)
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
            torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
@@ -507,19 +667,30 @@ def main():
             "tcp_accesses_per_gather": float(counters["L1 accesses per gather"]),
             "source": COUNTERS_PROFILE,
         }
+    if ceilings:
+        result["roofline"]["levels"] = level_fractions(total_steps / (ray_ms * 1e-3), int(m.info()["device_bytes"]),
+                                                       ceilings)
+        result["memory_ceilings"] = ceilings
     if not args.no_extras:
         cx = nbt.Context(0)            # default settings, untouched by the main line's tuning
         _log("measuring trajectory IG (config 4) ...")
-        result["trajectories"] = extra_trajectories(nbt, cx, reps=3)
+        result["trajectories"] = extra_trajectories(nbt, cx, reps=3, ceilings=ceilings)
         _log("measuring the batched launch (config 3) ...")
-        result["batched"] = extra_batch(nbt, cx, reps=5)
+        result["batched"] = extra_batch(nbt, cx, reps=5, ceilings=ceilings)
         _log("measuring the surrogate (config 5) ...")
         result["surrogate"] = extra_surrogate(nbt, cx)
         _log("measuring the map update by depth insertion ...")
         result["insert"] = extra_insert(nbt, cx, reps=5)
+        _log("measuring the runtime sweep at 1 cm voxels (compact) ...")
+        result["e1_sweep"] = {
+            "workload": "320^3 table-top map at 1 cm, N_P start points in the 1 m ball around an object top "
+                        "(Eq. 1), endpoint grid s_G x 1 cm on the far plane (75x65 deg, 1.5 m); GPU kernel and "
+                        "end-to-end (pose upload, evaluation, IG download) ms; the oracle at N_P = 100",
+            "rows": e1_sweep(nbt, cx, n_ps=(100, 500, 1000), oracle_n_ps=(100,), oracle_max_s=5.0)}
     if not args.no_cpu_baseline:
         _log("timing the CPU oracle baseline ...")
         result["cpu_baseline"] = cpu_baseline(scene, cam, poses, args.cpu_seconds)
+        result["cpu_baseline"]["other_workloads"] = finish_other_baselines(other_cpu)
     print(json.dumps(result), flush=True)
 
 

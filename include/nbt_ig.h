@@ -501,6 +501,27 @@ int nbt_ig_eval_cost(nbt_ig_ctx* ctx, const float* id_pos, const float* id_ig, u
 int nbt_ig_camera_from_grid(double fov_h, double fov_v, double d_cam, double s_vox, double s_g,
                             nbt_ig_camera* out);
 
+/* ---- memory probes (measurement of the ray kernels' ceilings) ----------------------
+ * Not part of the method: reads a caller's DEVICE buffer (16-byte aligned) with the
+ * access patterns of a voxel walk, so that a ray kernel's rate can be set against what
+ * the memory level holding a map of the same size delivers.  `sink` (DEVICE uint32
+ * [nbt_ig_probe_sink_words(ctx)]) receives one xor of the words read per workgroup.
+ *   NBT_IG_PROBE_STREAM       reads every 16-byte piece of buf, `count` passes;
+ *                             bytes/16 a power of two, count * bytes/16 < 2^32;
+ *                             useful bytes = count * bytes;
+ *   NBT_IG_PROBE_GATHER       8 * cu_count workgroups of 256 lanes, each lane reads
+ *                             `count` 4-byte words at pseudo-random positions;
+ *   NBT_IG_PROBE_QUAD_GATHER  the same, but the four lanes of a quad read the four
+ *                             words of one pseudo-random 16-byte piece;
+ *                             for both gathers bytes/4 is a power of two and useful
+ *                             bytes = 4 * count * 256 * 8 * cu_count. */
+#define NBT_IG_PROBE_STREAM 0
+#define NBT_IG_PROBE_GATHER 1
+#define NBT_IG_PROBE_QUAD_GATHER 2
+int nbt_ig_probe_sink_words(const nbt_ig_ctx* ctx);
+int nbt_ig_probe_memory(nbt_ig_ctx* ctx, int kind, const void* buf, size_t bytes, uint32_t count,
+                        uint32_t* sink, void* stream);
+
 const char* nbt_ig_status_string(int status);
 const char* nbt_ig_last_error(void);             /* thread-local; never NULL */
 int nbt_ig_abi_version(void);

@@ -86,6 +86,8 @@ _sig("nbt_ig_map_check", C.c_int, _vp, _vp)
 _sig("nbt_ig_map_info", C.c_int, _vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
      C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_size_t))
 _sig("nbt_ig_eval_viewpoints", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp, _vp)
+_sig("nbt_ig_probe_sink_words", C.c_int, _vp)
+_sig("nbt_ig_probe_memory", C.c_int, _vp, C.c_int, _vp, C.c_size_t, _u32, _vp, _vp)
 _sig("nbt_ig_eval_viewpoints_noalloc", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp, _vp)
 _sig("nbt_ig_eval_trajectories", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _u32, _vp, _vp, _vp, _vp)
 _sig("nbt_ig_ctx_set_lds_budget", C.c_int, _vp, C.c_size_t)
@@ -336,6 +338,20 @@ def eval_viewpoints(m: Map, cam, poses, ig_out=None, steps_out=None, stream=None
                                        _dev_ptr(ig_out, torch.float32, "ig_out"),
                                        _dev_ptr(steps_out, torch.int64, "steps_out"), _stream(stream)))
     return ig_out, steps_out
+
+
+PROBE_STREAM, PROBE_GATHER, PROBE_QUAD_GATHER = 0, 1, 2
+
+
+def probe_memory(ctx, kind, buf, count, sink=None, stream=None):
+    """nbt_ig_probe_memory over the bytes of device tensor ``buf``; returns the sink tensor."""
+    torch = _torch()
+    if sink is None:
+        sink = torch.empty(int(_lib.nbt_ig_probe_sink_words(ctx.handle)), dtype=torch.int32, device=buf.device)
+    _check(_lib.nbt_ig_probe_memory(ctx.handle, int(kind), _dev_ptr(buf, None, "buf"),
+                                    buf.numel() * buf.element_size(), int(count), _dev_ptr(sink, torch.int32, "sink"),
+                                    _stream(stream)))
+    return sink
 
 
 NOALLOC_MAX_VIEWPOINTS = 65536

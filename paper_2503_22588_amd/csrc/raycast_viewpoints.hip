@@ -134,14 +134,19 @@ __device__ __forceinline__ void vp_group(const DevMap& m, const CamParams& c,
         if (steps_out) steps_out[vp] = st;
         return;
     }
+    // The slot's fields are device-scope atomics.  A release fence orders them
+    // before the count (the last workgroup must see every sum), an acquire
+    // fence follows the count in the last workgroup only: a full fence in every
+    // workgroup would also invalidate its XCD's L2, which the map's gathers of
+    // every other workgroup there then miss.
     VpAccum* a = ws + vp;
     atomicAdd(&a->sum_fx, __double2ull_rn(tot * kFixScale));
     atomicAdd(&a->steps, st);
     if (inv) atomicOr(&a->invalid, 1u);
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const unsigned int done = atomicAdd(&a->count, 1u);
     if (done == groups - 1) {
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const unsigned long long s = atomicExch(&a->sum_fx, 0ull);
         const unsigned long long stp = atomicExch(&a->steps, 0ull);
         const unsigned int iv = atomicExch(&a->invalid, 0u);

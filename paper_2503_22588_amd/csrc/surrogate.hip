@@ -1,6 +1,7 @@
 // surrogate.hip -- learned IG surrogate: patch, conv3d trunk and MLP on BF16
-// MFMA (FP32 accumulation), top-k selection and the final pick after exact
-// rescoring.
+// MFMA (FP32 accumulation), radix selection of the candidates to rescore and
+// the final pick after exact rescoring; the bitonic top-k of the generic
+// selection call.
 //
 // Matrix fragments follow v_mfma_f32_16x16x32_bf16 (gfx950): for lane l,
 // A (16 x 32) row l%16 holds k = (l/16)*8 .. +7, B (32 x 16) column l%16 holds
@@ -57,83 +58,312 @@ __global__ __launch_bounds__(256) void patch_kernel(DevMap m, int f, int i0x, in
     }
 }
 
-// ---------------------------------------------------------------- conv -----
-// Implicit GEMM: out[n][m] = ReLU(bias[n] + sum_k W[n][k] A[m][k]) with m an
-// output position (z, y, x), k = ci*27 + (dz*3 + dy)*3 + dx and
-// A[m][k] = in[ci][2z+dz-1][2y+dy-1][2x+dx-1] (zero outside).  One workgroup
-// per 16 x 16 output tile; its S waves split the K = cin*27 reduction (chunk c
-// of 32 goes to wave c % S), and wave 0 adds the S partial tiles in a fixed
-// order, so the deep layers (few output tiles, long K) still spread over many
-// waves and the result does not depend on timing.  W is bf16 [cout][kpad],
-// zero padded to kpad.
-template <int S>
-__global__ __launch_bounds__(S * 64) void conv_kernel(const __bf16* __restrict__ in, int cin, int s_in,
-                                                      const __bf16* __restrict__ w,
-                                                      const float* __restrict__ bias, int cout, int kpad,
-                                                      __bf16* __restrict__ out) {
-    const int so = s_in / 2;
-    const int M = so * so * so;
-    const int ntiles = cout / 16;
-    const int tile = blockIdx.x;
-    const int mt = tile / ntiles, nt = tile - mt * ntiles;
-    const int wave = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    const int row = lane & 15, kq = lane >> 4;
-    const int m = mt * 16 + row;
-    const int z = m / (so * so), y = (m / so) % so, x = m % so;
-    const int K = cin * 27;
-    const int n = nt * 16 + row;
-    f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = wave * 32; k0 < kpad; k0 += S * 32) {
-        bf16x8_t a, b;
+// ---------------------------------------------------------------- trunk ----
+// The trunk in four launches.  trunk_front: workgroup b of 64 owns a 2^3 block
+// of the 8^3 conv2 outputs.  It counts the 11^3 patch cells that block
+// depends on (cells outside the 32^3 patch are conv1's zero padding) straight
+// from the map, rounds the fractions to BF16 in LDS, computes the 5^3 conv1
+// outputs around its block (those outside the 16^3 grid are conv2's zero
+// padding) and its eight conv2 positions, all from LDS, and stores them
+// channel-last, [z][y][x][32].  conv3, conv4 and the pose-independent part
+// of fc1 follow as three small launches that split each layer's weights
+// (the bulk of what the tail reads) over 4, 4 and 16 workgroups.  Kernel
+// boundaries order the steps: a device-scope fence in every workgroup would
+// write back and invalidate its XCD's L2 instead.
+//
+// conv2..conv4 are implicit GEMMs whose reduction index is tap-major,
+// k = tap * cin + ci (tap = (dz*3 + dy)*3 + dx), so that the 8 consecutive k
+// of one lane's MFMA fragment are 8 consecutive channels of one input voxel:
+// one 16-byte load from the channel-last activations.  The weights are
+// stored in that order, zero-padded to whole 32-wide k chunks.
+constexpr int kTrunkThreads = 1024;
+constexpr int kCells = 11;                        // patch cells per axis a block depends on
+constexpr int kCells3 = kCells * kCells * kCells;
+constexpr int kC1 = 5;                            // conv1 outputs per axis a block computes
+
+__device__ __forceinline__ bf16x8_t bf16_zero8() {
+    bf16x8_t z;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int k = k0 + kq * 8 + e;
-            __bf16 v = (__bf16)0.0f;
-            if (k < K && m < M) {
-                const int ci = k / 27, tap = k - ci * 27;
-                const int iz = 2 * z + tap / 9 - 1, iy = 2 * y + (tap / 3) % 3 - 1, ix = 2 * x + tap % 3 - 1;
-                if (iz >= 0 && iz < s_in && iy >= 0 && iy < s_in && ix >= 0 && ix < s_in)
-                    v = in[((size_t)ci * s_in + iz) * s_in * s_in + (size_t)iy * s_in + ix];
+    for (int e = 0; e < 8; ++e) z[e] = (__bf16)0.0f;
+    return z;
+}
+
+__device__ __forceinline__ __bf16 relu_bf16(float v) { return (__bf16)(v > 0.0f ? v : 0.0f); }
+
+__device__ __forceinline__ void tap_dxyz(int tap, int& dz, int& dy, int& dx) {
+    dz = tap / 9;
+    dy = (tap / 3) % 3;
+    dx = tap % 3;
+}
+
+// Occupied and unknown voxel counts of the 11^3 patch cells 8b-3 .. 8b+7 (per
+// axis) that block b depends on, added into cnt.  One thread per row of a
+// cell (F voxels along x); F = 0 reads the cell size at run time.
+template <int F>
+__device__ __forceinline__ void count_region(const TrunkArgs& p, int bx, int by, int bz,
+                                             unsigned (&cnt)[2][kCells3]) {
+    const int f = F > 0 ? F : p.f;
+    const int cx0 = 8 * bx - 3, cy0 = 8 * by - 3, cz0 = 8 * bz - 3;
+    const DevMap& m = p.m;
+    const int R = kCells * f;
+    const uint32_t rows = (uint32_t)R * (uint32_t)R * kCells;          // (z voxel, y voxel, x cell)
+    const __amdgpu_buffer_rsrc_t rs = map_rsrc(m);
+#pragma unroll 4
+    for (uint32_t r = threadIdx.x; r < rows; r += kTrunkThreads) {
+        const int clx = (int)(r % kCells);
+        const uint32_t q = r / kCells;
+        const int yv = (int)(q % (uint32_t)R), zv = (int)(q / (uint32_t)R);
+        const int cly = yv / f, clz = zv / f;
+        const int cx = cx0 + clx, cy = cy0 + cly, cz = cz0 + clz;
+        const int y = p.i0y + cy * f + (yv - cly * f), z = p.i0z + cz * f + (zv - clz * f);
+        const bool in_patch = (unsigned)cx < (unsigned)kGrid && (unsigned)cy < (unsigned)kGrid &&
+                              (unsigned)cz < (unsigned)kGrid;
+        const bool in_map = y >= 0 && y < m.ny && z >= 0 && z < m.nz;
+        if (!(in_patch && in_map)) continue;
+        const int x0 = p.i0x + cx * f;
+        uint32_t occ = 0, unk = 0;
+        if constexpr (F > 0) {
+#pragma unroll
+            for (int d = 0; d < F; ++d) {
+                const int x = x0 + d;
+                const uint32_t w = (x >= 0 && x < m.nx) ? load_word(rs, voxel_offset(m, x, y, z)) : 0u;
+                occ += (w & kOccBit) ? 1u : 0u;
+                unk += (w == kGainOne) ? 1u : 0u;
             }
-            a[e] = v;
+        } else {
+            const int xa = x0 < 0 ? 0 : x0, xb = x0 + f > m.nx ? m.nx : x0 + f;
+            for (int x = xa; x < xb; ++x) {
+                const uint32_t w = load_word(rs, voxel_offset(m, x, y, z));
+                occ += (w & kOccBit) ? 1u : 0u;
+                unk += (w == kGainOne) ? 1u : 0u;
+            }
         }
-        b = *reinterpret_cast<const bf16x8_t*>(w + (size_t)n * kpad + k0 + kq * 8);
-        acc = mfma16(a, b, acc);
+        const int cell = (clz * kCells + cly) * kCells + clx;
+        if (occ) atomicAdd(&cnt[0][cell], occ);
+        if (unk) atomicAdd(&cnt[1][cell], unk);
     }
-    if constexpr (S > 1) {
-        __shared__ f32x4_t part[S][64];
-        part[wave][lane] = acc;
-        __syncthreads();
-        if (wave != 0) return;
-#pragma unroll
-        for (int q = 1; q < S; ++q) acc += part[q][lane];
+}
+
+__global__ __launch_bounds__(kTrunkThreads) void trunk_front_kernel(TrunkArgs p) {
+    __shared__ unsigned s_cnt[2][kCells3];
+    __shared__ __bf16 s_patch[2][kCells3];
+    __shared__ __align__(16) __bf16 s_act1[kC1 * kC1 * kC1 * 16];
+    __shared__ f32x4_t s_part[8][64];
+
+    const int t = threadIdx.x;
+    const int wave = t >> 6, lane = t & 63, row = lane & 15, kq = lane >> 4;
+    const int bx = blockIdx.x & 3, by = (blockIdx.x >> 2) & 3, bz = blockIdx.x >> 4;
+
+    // ---- patch cells 8b-3 .. 8b+7 per axis: occupied and unknown counts ----
+    for (int i = t; i < kCells3; i += kTrunkThreads) s_cnt[0][i] = s_cnt[1][i] = 0u;
+    __syncthreads();
+    switch (p.f) {                    // a constant cell size lets the row loop unroll
+    case 1: count_region<1>(p, bx, by, bz, s_cnt); break;
+    case 2: count_region<2>(p, bx, by, bz, s_cnt); break;
+    case 3: count_region<3>(p, bx, by, bz, s_cnt); break;
+    case 4: count_region<4>(p, bx, by, bz, s_cnt); break;
+    case 5: count_region<5>(p, bx, by, bz, s_cnt); break;
+    case 6: count_region<6>(p, bx, by, bz, s_cnt); break;
+    case 8: count_region<8>(p, bx, by, bz, s_cnt); break;
+    default: count_region<0>(p, bx, by, bz, s_cnt); break;
     }
-    const int ncol = nt * 16 + row;
+    __syncthreads();
+    {
+        const float vol = (float)(p.f * p.f * p.f);
+        for (int i = t; i < kCells3; i += kTrunkThreads) {
+            s_patch[0][i] = (__bf16)((float)s_cnt[0][i] / vol);
+            s_patch[1][i] = (__bf16)((float)s_cnt[1][i] / vol);
+        }
+    }
+    __syncthreads();
+
+    // ---- conv1 outputs 4b-1 .. 4b+3 per axis (125 positions x 16 channels) ----
+    // k = ci*27 + tap (54, padded to 64); positions outside 0..15 are stored as 0
+    if (wave < 8) {
+        const int ml = wave * 16 + row;                                  // A row: local position
+        const int lz = ml / 25, ly = (ml / 5) % 5, lx = ml % 5;
+        f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int mo = mt * 16 + kq * 4 + r;
-        if (mo < M) {
-            const float v = acc[r] + bias[ncol];
-            out[(size_t)ncol * M + mo] = (__bf16)(v > 0.0f ? v : 0.0f);
+        for (int ch = 0; ch < 2; ++ch) {
+            bf16x8_t a;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = ch * 32 + kq * 8 + e;
+                __bf16 v = (__bf16)0.0f;
+                if (k < 54 && ml < kC1 * kC1 * kC1) {
+                    const int ci = k / 27;
+                    int dz, dy, dx;
+                    tap_dxyz(k - ci * 27, dz, dy, dx);
+                    v = s_patch[ci][((2 * lz + dz) * kCells + (2 * ly + dy)) * kCells + 2 * lx + dx];
+                }
+                a[e] = v;
+            }
+            const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(p.w[0] + row * 64 + ch * 32 + kq * 8);
+            acc = mfma16(a, b, acc);
+        }
+        const float bias = p.b[0][row];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int mo = wave * 16 + kq * 4 + r;
+            if (mo < kC1 * kC1 * kC1) {
+                const int oz = 4 * bz - 1 + mo / 25, oy = 4 * by - 1 + (mo / 5) % 5, ox = 4 * bx - 1 + mo % 5;
+                const bool inside = (unsigned)oz < 16u && (unsigned)oy < 16u && (unsigned)ox < 16u;
+                s_act1[mo * 16 + row] = inside ? relu_bf16(acc[r] + bias) : (__bf16)0.0f;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- conv2 outputs 2b .. 2b+1 per axis (8 positions x 32 channels) ----
+    // k = tap*16 + ci (432, padded to 448: 14 chunks); wave w: column tile w & 1,
+    // chunks w/2, w/2 + 4, ...; the four partial tiles added in a fixed order
+    if (wave < 8) {
+        const int nt = wave & 1, part = wave >> 1;
+        const int z = (row >> 2) & 1, y = (row >> 1) & 1, x = row & 1;      // rows 8..15 unused
+        f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const __bf16* wr = p.w[1] + (nt * 16 + row) * 448 + kq * 8;
+#pragma unroll
+        for (int ch = part; ch < 14; ch += 4) {
+            const int tap = 2 * ch + (kq >> 1), c0 = (kq & 1) * 8;
+            bf16x8_t a = bf16_zero8();
+            if (tap < 27 && row < 8) {
+                int dz, dy, dx;
+                tap_dxyz(tap, dz, dy, dx);
+                a = *reinterpret_cast<const bf16x8_t*>(
+                    s_act1 + (((2 * z + dz) * kC1 + (2 * y + dy)) * kC1 + 2 * x + dx) * 16 + c0);
+            }
+            const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(wr + ch * 32);
+            acc = mfma16(a, b, acc);
+        }
+        s_part[wave][lane] = acc;
+    }
+    __syncthreads();
+    if (wave < 2) {
+        const f32x4_t acc = ((s_part[wave][lane] + s_part[wave + 2][lane]) + s_part[wave + 4][lane]) +
+                            s_part[wave + 6][lane];
+        const int n = wave * 16 + row;
+        const float bias = p.b[1][n];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int mo = kq * 4 + r;
+            if (mo < 8) {
+                const int oz = 2 * bz + (mo >> 2), oy = 2 * by + ((mo >> 1) & 1), ox = 2 * bx + (mo & 1);
+                p.act2[((oz * 8 + oy) * 8 + ox) * 32 + n] = relu_bf16(acc[r] + bias);
+            }
+        }
+    }
+
+}
+
+// conv3: 8^3 x 32 -> 4^3 x 64, k = tap*32 + ci (864).  Workgroup j owns output
+// channels 16j..16j+15 (its weights, 27 KiB, are read by it alone), wave w
+// the positions 16w..16w+15; conv2's output is staged in LDS.
+__global__ __launch_bounds__(256) void trunk_conv3_kernel(TrunkArgs p) {
+    __shared__ __align__(16) __bf16 s_act2[512 * 32];
+    const int t = threadIdx.x;
+    const int wave = t >> 6, lane = t & 63, row = lane & 15, kq = lane >> 4;
+    const int nt = blockIdx.x;
+    bf16x8_t b3[27];                                  // requested before the staging
+    {
+        const __bf16* wr = p.w[2] + (nt * 16 + row) * 864 + kq * 8;
+#pragma unroll
+        for (int tap = 0; tap < 27; ++tap) b3[tap] = *reinterpret_cast<const bf16x8_t*>(wr + tap * 32);
+    }
+    for (int i = t; i < 512 * 32 / 8; i += 256)
+        reinterpret_cast<bf16x8_t*>(s_act2)[i] = reinterpret_cast<const bf16x8_t*>(p.act2)[i];
+    __syncthreads();
+    const int mm = wave * 16 + row;
+    const int z = mm >> 4, y = (mm >> 2) & 3, x = mm & 3;
+    f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int tap = 0; tap < 27; ++tap) {
+        int dz, dy, dx;
+        tap_dxyz(tap, dz, dy, dx);
+        const int iz = 2 * z + dz - 1, iy = 2 * y + dy - 1, ix = 2 * x + dx - 1;
+        bf16x8_t a = bf16_zero8();
+        if ((unsigned)iz < 8u && (unsigned)iy < 8u && (unsigned)ix < 8u)
+            a = *reinterpret_cast<const bf16x8_t*>(s_act2 + ((iz * 8 + iy) * 8 + ix) * 32 + kq * 8);
+        acc = mfma16(a, b3[tap], acc);
+    }
+    const int n = nt * 16 + row;
+    const float bias = p.b[2][n];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) p.act3[(wave * 16 + kq * 4 + r) * 64 + n] = relu_bf16(acc[r] + bias);
+}
+
+// conv4: 4^3 x 64 -> 2^3 x 64, k = tap*64 + ci (1728).  Workgroup j owns
+// output channels 16j..16j+15; its four waves split the 54 k chunks and add
+// their partial tiles in a fixed order.  Writes the 512 features (BF16),
+// index c*8 + z*4 + y*2 + x.
+__global__ __launch_bounds__(256) void trunk_conv4_kernel(TrunkArgs p) {
+    __shared__ __align__(16) __bf16 s_act3[64 * 64];
+    __shared__ f32x4_t s_part[4][64];
+    const int t = threadIdx.x;
+    const int wave = t >> 6, lane = t & 63, row = lane & 15, kq = lane >> 4;
+    const int nt = blockIdx.x;
+    bf16x8_t b4[14];                                  // chunks wave, wave + 4, ...
+    {
+        const __bf16* wr = p.w[3] + (nt * 16 + row) * 1728 + kq * 8;
+#pragma unroll
+        for (int i = 0; i < 14; ++i) {
+            const int ch = wave + 4 * i;
+            b4[i] = ch < 54 ? *reinterpret_cast<const bf16x8_t*>(wr + ch * 32) : bf16_zero8();
+        }
+    }
+    for (int i = t; i < 64 * 64 / 8; i += 256)
+        reinterpret_cast<bf16x8_t*>(s_act3)[i] = reinterpret_cast<const bf16x8_t*>(p.act3)[i];
+    __syncthreads();
+    const int z = (row >> 2) & 1, y = (row >> 1) & 1, x = row & 1;      // rows 8..15 unused
+    f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int i = 0; i < 14; ++i) {
+        const int ch = wave + 4 * i;
+        if (ch < 54) {
+            const int tap = ch >> 1, c0 = (ch & 1) * 32 + kq * 8;
+            int dz, dy, dx;
+            tap_dxyz(tap, dz, dy, dx);
+            const int iz = 2 * z + dz - 1, iy = 2 * y + dy - 1, ix = 2 * x + dx - 1;
+            bf16x8_t a = bf16_zero8();
+            if (row < 8 && (unsigned)iz < 4u && (unsigned)iy < 4u && (unsigned)ix < 4u)
+                a = *reinterpret_cast<const bf16x8_t*>(s_act3 + ((iz * 4 + iy) * 4 + ix) * 64 + c0);
+            acc = mfma16(a, b4[i], acc);
+        }
+    }
+    s_part[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0) {
+        const f32x4_t sum = ((s_part[0][lane] + s_part[1][lane]) + s_part[2][lane]) + s_part[3][lane];
+        const int n = nt * 16 + row;
+        const float bias = p.b[3][n];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int mo = kq * 4 + r;                // position z*4 + y*2 + x
+            if (mo < 8) p.feat[n * 8 + mo] = relu_bf16(sum[r] + bias);
         }
     }
 }
 
-// c[n] = b1[n] + sum_k W1f[n][k] f[k]: the pose-independent part of fc1.
-// Sixteen lanes per output: lane j sums k = j, j + 16, ... (32 terms), then a
-// fixed butterfly adds the sixteen partial sums.
-__global__ __launch_bounds__(256) void fc1_feature_kernel(const __bf16* __restrict__ feat,
-                                                          const __bf16* __restrict__ w1f,
-                                                          const float* __restrict__ b1,
-                                                          float* __restrict__ c) {
-    const int n = blockIdx.x * 16 + (threadIdx.x >> 4);
-    const int j = threadIdx.x & 15;
-    float s = 0.0f;
-    for (int k = j; k < kFeat; k += 16) s += (float)w1f[(size_t)n * kFeat + k] * (float)feat[k];
+// c[n] = b1[n] + sum_k W1f[n][k] f[k] (the pose-independent part of fc1):
+// workgroup j owns outputs 16j..16j+15, sixteen lanes per output with 32 k
+// each, added by a fixed butterfly.
+__global__ __launch_bounds__(256) void trunk_fc1_kernel(TrunkArgs p) {
+    const int t = threadIdx.x;
+    const int n = blockIdx.x * 16 + (t >> 4), q = t & 15;
+    const __bf16* wr = p.w1f + (size_t)n * kFeat + q * 32;
+    bf16x8_t w[4], f[4];
 #pragma unroll
-    for (int d = 8; d >= 1; d >>= 1) s += __shfl_xor(s, d, 16);
-    if (j == 0) c[n] = b1[n] + s;
+    for (int i = 0; i < 4; ++i) {
+        w[i] = *reinterpret_cast<const bf16x8_t*>(wr + 8 * i);
+        f[i] = *reinterpret_cast<const bf16x8_t*>(p.feat + q * 32 + 8 * i);
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s += (float)w[i][e] * (float)f[i][e];
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) s += __shfl_xor(s, o, 16);
+    if (q == 0) p.c[n] = p.fb1[n] + s;
 }
 
 // ---------------------------------------------------------------- MLP ------
@@ -141,10 +371,25 @@ __global__ __launch_bounds__(256) void fc1_feature_kernel(const __bf16* __restri
 // b2) on MFMA with W2 staged in LDS (rows padded to 264 halves so the 16
 // lanes reading one k-slice of 16 rows hit distinct banks), y = out_scale *
 // (W3 . h2 + b3).  One workgroup of 8 waves per CU shares the LDS copy of W2
-// (and of c, W1d, b2, W3); each wave takes 16 poses at a time.
+// (and of c, W1d, b2, W3); each wave takes 32 poses at a time, two 16-row A
+// tiles that share every W2 fragment read from LDS.
 constexpr int kW2Stride = kHidden + 8;
 constexpr int kMlpWaves = 8;
-constexpr size_t kMlpLds = (size_t)kHidden * kW2Stride * sizeof(__bf16) + (size_t)kHidden * 7 * sizeof(float);
+// W1d rows in LDS: 4 floats per neuron plus 4 of padding after every 16, so
+// that the four neurons k, k+8, k+16, k+24 one instruction reads (one per
+// 16-lane group) fall in different banks
+constexpr int kW1dWords = 4 * kHidden + 4 * (kHidden / 16);
+__device__ __forceinline__ int w1d_slot(int k) { return 4 * k + 4 * (k >> 4); }
+constexpr size_t kMlpLds = (size_t)kHidden * kW2Stride * sizeof(__bf16) + (size_t)(kW1dWords + 3 * kHidden) * sizeof(float);
+
+// Rank key of a value: larger values give larger keys, -0 and +0 the same
+// key, NaN the smallest.
+__device__ __forceinline__ uint32_t mono_key(float v) {
+    const uint32_t b = __float_as_uint(v);
+    if (v != v) return 0u;
+    if (v == 0.0f) return 0x80000000u;
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
 
 __global__ __launch_bounds__(kMlpWaves * 64) void mlp_kernel(const float* __restrict__ poses, uint32_t n,
                                                              float px, float py, float pz, float dist_mean,
@@ -157,7 +402,7 @@ __global__ __launch_bounds__(kMlpWaves * 64) void mlp_kernel(const float* __rest
     extern __shared__ __align__(16) unsigned char smem[];
     __bf16* sw2 = reinterpret_cast<__bf16*>(smem);
     float* sw1d = reinterpret_cast<float*>(smem + (size_t)kHidden * kW2Stride * sizeof(__bf16));
-    float* sc = sw1d + 4 * kHidden;
+    float* sc = sw1d + kW1dWords;
     float* sb2 = sc + kHidden;
     float* sw3 = sb2 + kHidden;
     for (int i = threadIdx.x; i < kHidden * kHidden / 8; i += blockDim.x) {
@@ -166,7 +411,7 @@ __global__ __launch_bounds__(kMlpWaves * 64) void mlp_kernel(const float* __rest
             *reinterpret_cast<const bf16x8_t*>(w2 + (size_t)r * kHidden + k);
     }
     for (int i = threadIdx.x; i < kHidden; i += blockDim.x) {
-        *reinterpret_cast<float4*>(sw1d + 4 * i) = *reinterpret_cast<const float4*>(w1d + 4 * i);
+        *reinterpret_cast<float4*>(sw1d + w1d_slot(i)) = *reinterpret_cast<const float4*>(w1d + 4 * i);
         sc[i] = c[i];
         sb2[i] = b2[i];
         sw3[i] = w3[i];
@@ -175,76 +420,304 @@ __global__ __launch_bounds__(kMlpWaves * 64) void mlp_kernel(const float* __rest
 
     const int lane = threadIdx.x & 63;
     const int row = lane & 15, kq = lane >> 4;
-    const uint32_t ntile = (n + 15) / 16;
+    const uint32_t ngroup = (n + 31) / 32;
     const uint32_t wave_global = blockIdx.x * kMlpWaves + (threadIdx.x >> 6);
     const uint32_t waves = gridDim.x * kMlpWaves;
-    for (uint32_t t = wave_global; t < ntile; t += waves) {
-        const uint32_t p = t * 16 + row;
-        float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f, dn = 0.0f;
-        if (p < n) {
-            const float vx = poses[12 * (size_t)p + 9] - px;
-            const float vy = poses[12 * (size_t)p + 10] - py;
-            const float vz = poses[12 * (size_t)p + 11] - pz;
-            const float d = sqrtf(vx * vx + vy * vy + vz * vz);
-            const float inv = d > 0.0f ? 1.0f / d : 0.0f;
-            u0 = vx * inv;
-            u1 = vy * inv;
-            u2 = vz * inv;
-            dn = (d - dist_mean) / dist_scale;
+    for (uint32_t g = wave_global; g < ngroup; g += waves) {
+        float u0[2], u1[2], u2[2], dn[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const uint32_t p = g * 32 + i * 16 + row;
+            u0[i] = u1[i] = u2[i] = dn[i] = 0.0f;
+            if (p < n) {
+                const float vx = poses[12 * (size_t)p + 9] - px;
+                const float vy = poses[12 * (size_t)p + 10] - py;
+                const float vz = poses[12 * (size_t)p + 11] - pz;
+                const float d = sqrtf(vx * vx + vy * vy + vz * vz);
+                const float inv = d > 0.0f ? 1.0f / d : 0.0f;
+                u0[i] = vx * inv;
+                u1[i] = vy * inv;
+                u2[i] = vz * inv;
+                dn[i] = (d - dist_mean) / dist_scale;
+            }
         }
         // output-stationary: the 16 column tiles of h2 stay in registers while
         // h1 is produced one 32-wide k-slice at a time
-        f32x4_t acc[kHidden / 16];
+        f32x4_t acc[2][kHidden / 16];
 #pragma unroll
-        for (int nt = 0; nt < kHidden / 16; ++nt) acc[nt] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 2
+        for (int nt = 0; nt < kHidden / 16; ++nt) acc[0][nt] = acc[1][nt] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 1
         for (int ks = 0; ks < kHidden / 32; ++ks) {
-            bf16x8_t a;
+            bf16x8_t a[2];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int k = ks * 32 + kq * 8 + e;
-                const float4 wd = *reinterpret_cast<const float4*>(sw1d + 4 * k);
-                float h = sc[k] + wd.x * u0 + wd.y * u1 + wd.z * u2 + wd.w * dn;
-                a[e] = (__bf16)(h > 0.0f ? h : 0.0f);
+                const float4 wd = *reinterpret_cast<const float4*>(sw1d + w1d_slot(k));
+                const float ck = sc[k];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    // fused multiply-adds: one rounding per term (the library is
+                    // otherwise built without contraction)
+                    float h = __builtin_fmaf(wd.x, u0[i], ck);
+                    h = __builtin_fmaf(wd.y, u1[i], h);
+                    h = __builtin_fmaf(wd.z, u2[i], h);
+                    h = __builtin_fmaf(wd.w, dn[i], h);
+                    a[i][e] = (__bf16)(h > 0.0f ? h : 0.0f);
+                }
             }
             const __bf16* bk = sw2 + row * kW2Stride + ks * 32 + kq * 8;
 #pragma unroll
-            for (int nt = 0; nt < kHidden / 16; ++nt)
-                acc[nt] = mfma16(a, *reinterpret_cast<const bf16x8_t*>(bk + nt * 16 * kW2Stride), acc[nt]);
-        }
-        float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int nt = 0; nt < kHidden / 16; ++nt) {
-            const int col = nt * 16 + row;
-            const float bb = sb2[col], ww = sw3[col];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float h2 = acc[nt][r] + bb;
-                part[r] += ww * (h2 > 0.0f ? h2 : 0.0f);
+            for (int nt = 0; nt < kHidden / 16; ++nt) {
+                const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(bk + nt * 16 * kW2Stride);
+                acc[0][nt] = mfma16(a[0], b, acc[0][nt]);
+                acc[1][nt] = mfma16(a[1], b, acc[1][nt]);
             }
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int i = 0; i < 2; ++i) {
+            float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int o = 1; o < 16; o <<= 1) part[r] += __shfl_xor(part[r], o, 64);
-        }
-        if (row == 0) {
+            for (int nt = 0; nt < kHidden / 16; ++nt) {
+                const int col = nt * 16 + row;
+                const float bb = sb2[col], ww = sw3[col];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float h2 = acc[i][nt][r] + bb;
+                    part[r] = __builtin_fmaf(ww, h2 > 0.0f ? h2 : 0.0f, part[r]);
+                }
+            }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const uint32_t q = t * 16 + kq * 4 + r;
-                if (q < n) pred[q] = out_scale * (part[r] + b3);
+#pragma unroll
+                for (int o = 1; o < 16; o <<= 1) part[r] += __shfl_xor(part[r], o, 64);
+            }
+            if (row == 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const uint32_t q = g * 32 + i * 16 + kq * 4 + r;
+                    if (q < n) pred[q] = out_scale * (part[r] + b3);
+                }
             }
         }
     }
 }
 
+// ------------------------------------------------------- radix selection ----
+// The k largest of n predictions (ties to the lower index) as a set, with
+// their poses for the exact rescoring, in stages of one 1024-thread
+// workgroup per slice of items.  A workgroup holds its items in registers
+// (R per thread) and finds the exact k-th rank key T by three histogram
+// digits of the key (bits 31..20, 19..8, 7..0), each over the items still
+// tied with the bins chosen so far; of the keys equal to T it takes the
+// lowest indices, found by two histograms of index bits when more are equal
+// than needed.  Stage workgroups keep the k best of 4096 items each; the
+// last stage (one workgroup, at most 16,384 items) writes the chosen
+// candidates and copies their poses.  Sets are written in no particular
+// order: the final pick after rescoring orders by exact IG and index.
+constexpr int kSelThreads = 1024;
+constexpr uint32_t kNoItem = 0xFFFFFFFFu;         // index of an empty slot
+constexpr uint32_t kStageSlice = 4096;            // items per stage workgroup (4 per thread)
+constexpr uint32_t kFinalItems = 16384;           // items of the last stage (16 per thread)
+
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_wave, uint32_t& total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_wave[wave] = x;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kSelThreads / 64; ++w) {
+        const uint32_t s = s_wave[w];
+        base += (w < wave) ? s : 0u;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return base + x - v;
+}
+
+// Bins 4t..4t+3 of s_hist (`bins` of them) per thread; the histogram is left
+// zero.  DESC: the bin d with (items in bins above d) < need <= (items in
+// bins d and above); otherwise counted from the lowest bin.  Returns d; sets
+// beyond = the items strictly beyond d, in_bin = the items in d, total.
+template <bool DESC>
+__device__ __forceinline__ uint32_t find_bin(uint32_t* s_hist, uint32_t bins, uint32_t need, uint32_t* s_wave,
+                                             uint32_t* s_out, uint32_t& beyond, uint32_t& in_bin,
+                                             uint32_t& total) {
+    uint32_t h[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) h[q] = 4 * threadIdx.x + q < bins ? s_hist[4 * threadIdx.x + q] : 0u;
+    const uint32_t v = h[0] + h[1] + h[2] + h[3];
+    const uint32_t ex = block_excl_scan(v, s_wave, total);     // (its barriers order the reads above)
+    for (uint32_t i = threadIdx.x; i < bins; i += kSelThreads) s_hist[i] = 0u;
+    uint32_t run = DESC ? total - ex - v : ex;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int q = DESC ? 3 - i : i;
+        if (run < need && run + h[q] >= need) {
+            s_out[0] = 4u * threadIdx.x + q;
+            s_out[1] = run;
+            s_out[2] = h[q];
+        }
+        run += h[q];
+    }
+    __syncthreads();
+    const uint32_t d = s_out[0];
+    beyond = s_out[1];
+    in_bin = s_out[2];
+    __syncthreads();
+    return d;
+}
+
+// Calls emit(key, idx) once for each of the k best valid items the workgroup
+// holds (all of them when there are at most k).
+template <int R, class EMIT>
+__device__ __forceinline__ void block_select(const uint32_t (&key)[R], const uint32_t (&idx)[R], uint32_t k,
+                                             uint32_t* s_hist, uint32_t* s_wave, uint32_t* s_out, EMIT emit) {
+    uint32_t beyond, in_bin, total;
+    // digit 1: bits 31..20
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (idx[r] != kNoItem) atomicAdd(&s_hist[key[r] >> 20], 1u);
+    __syncthreads();
+    const uint32_t d1 = find_bin<true>(s_hist, 4096, k, s_wave, s_out, beyond, in_bin, total);
+    if (total <= k) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (idx[r] != kNoItem) emit(key[r], idx[r]);
+        return;
+    }
+    uint32_t need = k - beyond;
+    // digit 2: bits 19..8 of the keys in bin d1
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (idx[r] != kNoItem && (key[r] >> 20) == d1) atomicAdd(&s_hist[(key[r] >> 8) & 0xFFFu], 1u);
+    __syncthreads();
+    const uint32_t p2 = (d1 << 12) | find_bin<true>(s_hist, 4096, need, s_wave, s_out, beyond, in_bin, total);
+    need -= beyond;
+    // digit 3: bits 7..0
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (idx[r] != kNoItem && (key[r] >> 8) == p2) atomicAdd(&s_hist[key[r] & 0xFFu], 1u);
+    __syncthreads();
+    const uint32_t T = (p2 << 8) | find_bin<true>(s_hist, 256, need, s_wave, s_out, beyond, in_bin, total);
+    need -= beyond;                                   // 1 <= need <= in_bin: keys equal to T to take
+    uint32_t imax = kNoItem;
+    if (in_bin > need) {
+        // the need lowest indices among the keys equal to T (index < 2^22)
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (idx[r] != kNoItem && key[r] == T) atomicAdd(&s_hist[idx[r] >> 11], 1u);
+        __syncthreads();
+        const uint32_t hi = find_bin<false>(s_hist, 2048, need, s_wave, s_out, beyond, in_bin, total);
+        need -= beyond;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (idx[r] != kNoItem && key[r] == T && (idx[r] >> 11) == hi) atomicAdd(&s_hist[idx[r] & 0x7FFu], 1u);
+        __syncthreads();
+        imax = (hi << 11) | find_bin<false>(s_hist, 2048, need, s_wave, s_out, beyond, in_bin, total);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (idx[r] != kNoItem && (key[r] > T || (key[r] == T && idx[r] <= imax))) emit(key[r], idx[r]);
+}
+
+// One stage: workgroup b takes items 4096 b .. 4096 b + 4095 (predictions
+// when FROM_PRED, else the previous stage's keys and indices) and writes its
+// k best to slots k b .. k b + k - 1 (empty slots marked kNoItem).
+template <bool FROM_PRED>
+__global__ __launch_bounds__(kSelThreads) void select_stage_kernel(const float* __restrict__ pred,
+                                                                   const uint32_t* __restrict__ in_key,
+                                                                   const uint32_t* __restrict__ in_idx,
+                                                                   uint32_t count, uint32_t k,
+                                                                   uint32_t* __restrict__ out_key,
+                                                                   uint32_t* __restrict__ out_idx) {
+    __shared__ uint32_t s_hist[4096];
+    __shared__ uint32_t s_wave[kSelThreads / 64];
+    __shared__ uint32_t s_out[3];
+    __shared__ uint32_t s_count;
+    const uint32_t t = threadIdx.x;
+    for (uint32_t i = t; i < 4096; i += kSelThreads) s_hist[i] = 0u;
+    if (t == 0) s_count = 0u;
+    uint32_t key[4], idx[4];
+    const uint32_t i0 = blockIdx.x * kStageSlice + 4u * t;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint32_t i = i0 + r;
+        if (FROM_PRED) {
+            key[r] = i < count ? mono_key(pred[i]) : 0u;
+            idx[r] = i < count ? i : kNoItem;
+        } else {
+            key[r] = i < count ? in_key[i] : 0u;
+            idx[r] = i < count ? in_idx[i] : kNoItem;
+        }
+    }
+    __syncthreads();
+    uint32_t* ok = out_key + (size_t)blockIdx.x * k;
+    uint32_t* oi = out_idx + (size_t)blockIdx.x * k;
+    block_select<4>(key, idx, k, s_hist, s_wave, s_out, [&](uint32_t kk, uint32_t ii) {
+        const uint32_t p = atomicAdd(&s_count, 1u);
+        if (p < k) {
+            ok[p] = kk;
+            oi[p] = ii;
+        }
+    });
+    __syncthreads();
+    for (uint32_t p = s_count + t; p < k; p += kSelThreads) {
+        ok[p] = 0u;
+        oi[p] = kNoItem;
+    }
+}
+
+// The last stage (one workgroup, count <= 1024 R): the k best become the
+// candidates, with their poses.
+template <bool FROM_PRED, int R>
+__global__ __launch_bounds__(kSelThreads) void select_final_kernel(const float* __restrict__ pred,
+                                                                   const uint32_t* __restrict__ in_key,
+                                                                   const uint32_t* __restrict__ in_idx,
+                                                                   uint32_t count, uint32_t k,
+                                                                   const float* __restrict__ poses,
+                                                                   uint32_t* __restrict__ cand,
+                                                                   float* __restrict__ cand_poses) {
+    __shared__ uint32_t s_hist[4096];
+    __shared__ uint32_t s_wave[kSelThreads / 64];
+    __shared__ uint32_t s_out[3];
+    __shared__ uint32_t s_count;
+    const uint32_t t = threadIdx.x;
+    for (uint32_t i = t; i < 4096; i += kSelThreads) s_hist[i] = 0u;
+    if (t == 0) s_count = 0u;
+    uint32_t key[R], idx[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t i = (uint32_t)r * kSelThreads + t;           // coalesced
+        if (FROM_PRED) {
+            key[r] = i < count ? mono_key(pred[i]) : 0u;
+            idx[r] = i < count ? i : kNoItem;
+        } else {
+            key[r] = i < count ? in_key[i] : 0u;
+            idx[r] = i < count ? in_idx[i] : kNoItem;
+        }
+    }
+    __syncthreads();
+    block_select<R>(key, idx, k, s_hist, s_wave, s_out, [&](uint32_t, uint32_t ii) {
+        const uint32_t p = atomicAdd(&s_count, 1u);
+        if (p < k) {
+            cand[p] = ii;
+            for (int e = 0; e < 12; ++e) cand_poses[12 * (size_t)p + e] = poses[12 * (size_t)ii + e];
+        }
+    });
+}
+
 // ---------------------------------------------------------------- top-k ----
 // Keys order candidates by value (descending) and index (ascending on ties):
-// (monotone bits of the value) << 32 | ~index.  NaN ranks below everything.
+// mono_key(value) << 32 | ~index.  NaN ranks below everything.
 __device__ __forceinline__ unsigned long long rank_key(float v, uint32_t idx) {
-    uint32_t b = __float_as_uint(v);
-    b = (v != v) ? 0u : ((b & 0x80000000u) ? ~b : (b | 0x80000000u));
-    return ((unsigned long long)b << 32) | (unsigned long long)(0xFFFFFFFFu - idx);
+    return ((unsigned long long)mono_key(v) << 32) | (unsigned long long)(0xFFFFFFFFu - idx);
 }
 
 // Bitonic sort, descending, of N = 1024 R keys held by a 1024-thread block,
@@ -381,33 +854,35 @@ __global__ __launch_bounds__(1024) void topk_final_kernel(const float* __restric
     }
 }
 
-__global__ void gather_poses_kernel(const float* __restrict__ poses, const uint32_t* __restrict__ idx,
-                                    uint32_t k, float* __restrict__ out) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < k * 12) out[i] = poses[12 * (size_t)idx[i / 12] + i % 12];
-}
-
 // Final pick among the rescored candidates: best exact IG first, ties to the
 // lower candidate index.  Slot j holds candidate cand[j] with IG ig_exact[j];
-// the key carries the slot so the IG is read back without a search.
-__global__ __launch_bounds__(1024) void final_select_kernel(const float* __restrict__ ig_exact,
-                                                            const uint32_t* __restrict__ cand,
-                                                            uint32_t kr, uint32_t k,
-                                                            uint32_t* __restrict__ idx_out,
-                                                            float* __restrict__ ig_out) {
-    __shared__ unsigned long long s[kMaxRescore];
+// keys are distinct (the candidate index is in the low word), so each slot's
+// rank is the number of larger keys, and the k best write themselves.
+__global__ __launch_bounds__(kMaxRescore) void final_select_kernel(const float* __restrict__ ig_exact,
+                                                                   const uint32_t* __restrict__ cand,
+                                                                   uint32_t kr, uint32_t k,
+                                                                   uint32_t* __restrict__ idx_out,
+                                                                   float* __restrict__ ig_out) {
+    __shared__ __align__(16) unsigned long long s_key[kMaxRescore + 2];
     const uint32_t i = threadIdx.x;
-    // low word: candidate index (< 2^22) above the slot (< 2^10), complemented
-    unsigned long long key[1];
-    key[0] = i < kr ? ((rank_key(ig_exact[i], 0u) & 0xFFFFFFFF00000000ull) |
-                       (unsigned long long)(0xFFFFFFFFu - ((cand[i] << 10) | i)))
-                    : 0ull;
-    sort_desc_block<1>(key, s);
-    if (i < k) {
-        const uint32_t low = 0xFFFFFFFFu - (uint32_t)(key[0] & 0xFFFFFFFFull);
-        const uint32_t slot = low & 1023u;
-        idx_out[i] = cand[slot];
-        ig_out[i] = ig_exact[slot];
+    unsigned long long key = 0ull;
+    if (i < kr) {
+        key = rank_key(ig_exact[i], cand[i]);
+        s_key[i] = key;
+    }
+    if (i == 0 && (kr & 1u)) s_key[kr] = 0ull;       // pads an odd count: ranks above no key
+    __syncthreads();
+    if (i >= kr) return;
+    uint32_t rank = 0;
+    const ulonglong2* kp = reinterpret_cast<const ulonglong2*>(s_key);
+#pragma unroll 4
+    for (uint32_t j = 0; j < (kr + 1) / 2; ++j) {
+        const ulonglong2 kk = kp[j];
+        rank += (kk.x > key ? 1u : 0u) + (kk.y > key ? 1u : 0u);
+    }
+    if (rank < k) {
+        idx_out[rank] = cand[i];
+        ig_out[rank] = ig_exact[i];
     }
 }
 
@@ -420,28 +895,15 @@ hipError_t launch_patch(const DevMap& m, int f, const int i0[3], __bf16* out_bf1
     return hipGetLastError();
 }
 
-hipError_t launch_conv(const __bf16* in, int cin, int s_in, const __bf16* w, const float* bias, int cout,
-                       int kpad, __bf16* out, hipStream_t s) {
-    const int so = s_in / 2, M = so * so * so;
-    const int tiles = ((M + 15) / 16) * (cout / 16);
-    const int chunks = kpad / 32;
-    // waves per tile: about two K chunks each, at most 16
-    if (chunks >= 32)
-        hipLaunchKernelGGL(conv_kernel<16>, dim3(tiles), dim3(16 * 64), 0, s, in, cin, s_in, w, bias, cout, kpad, out);
-    else if (chunks >= 16)
-        hipLaunchKernelGGL(conv_kernel<8>, dim3(tiles), dim3(8 * 64), 0, s, in, cin, s_in, w, bias, cout, kpad, out);
-    else if (chunks >= 8)
-        hipLaunchKernelGGL(conv_kernel<4>, dim3(tiles), dim3(4 * 64), 0, s, in, cin, s_in, w, bias, cout, kpad, out);
-    else if (chunks >= 4)
-        hipLaunchKernelGGL(conv_kernel<2>, dim3(tiles), dim3(2 * 64), 0, s, in, cin, s_in, w, bias, cout, kpad, out);
-    else
-        hipLaunchKernelGGL(conv_kernel<1>, dim3(tiles), dim3(64), 0, s, in, cin, s_in, w, bias, cout, kpad, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_fc1_feature(const __bf16* feat, const __bf16* w1f, const float* b1, float* c,
-                              hipStream_t s) {
-    hipLaunchKernelGGL(fc1_feature_kernel, dim3(kHidden / 16), dim3(256), 0, s, feat, w1f, b1, c);
+hipError_t launch_trunk(const TrunkArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(trunk_front_kernel, dim3(kTrunkBlocks), dim3(kTrunkThreads), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(trunk_conv3_kernel, dim3(4), dim3(256), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(trunk_conv4_kernel, dim3(4), dim3(256), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(trunk_fc1_kernel, dim3(kHidden / 16), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -453,13 +915,61 @@ hipError_t launch_mlp(const float* poses, uint32_t n, const float poi[3], float 
     static std::atomic<size_t> lds_set[64];
     hipError_t e = allow_dynamic_lds((const void*)mlp_kernel, lds, lds_set, 64);
     if (e != hipSuccess) return e;
-    const uint32_t tiles = (n + 15) / 16;
-    uint32_t blocks = (tiles + kMlpWaves - 1) / kMlpWaves;
+    const uint32_t groups = (n + 31) / 32;
+    uint32_t blocks = (groups + kMlpWaves - 1) / kMlpWaves;
     const uint32_t cap = (uint32_t)cu_count;     // one block per CU holds W2 in its LDS
     if (blocks > cap) blocks = cap;
     if (blocks == 0) blocks = 1;
     hipLaunchKernelGGL(mlp_kernel, dim3(blocks), dim3(kMlpWaves * 64), lds, s, poses, n, poi[0], poi[1], poi[2],
                        dist_mean, dist_scale, c, w1d, w2, b2, w3, b3, out_scale, pred);
+    return hipGetLastError();
+}
+
+// Stage outputs of n items: k slots per 4096 items, and again until at most
+// kFinalItems remain.
+size_t select_scratch_items(uint32_t n, uint32_t k) {
+    size_t most = 0;
+    uint64_t count = n;
+    while (count > kFinalItems) {
+        count = (count + kStageSlice - 1) / kStageSlice * k;
+        if (count > most) most = count;               // k <= 1024: each stage keeps at most a quarter
+    }
+    return most;
+}
+
+hipError_t launch_select(const float* pred, uint32_t n, uint32_t k, const float* poses, uint32_t* scratch,
+                         size_t scratch_items, uint32_t* cand, float* cand_poses, hipStream_t s) {
+    const uint32_t* in_key = nullptr;
+    const uint32_t* in_idx = nullptr;
+    uint32_t count = n;
+    int flip = 0;
+    while (count > kFinalItems) {
+        const uint32_t blocks = (count + kStageSlice - 1) / kStageSlice;
+        uint32_t* ok = scratch + (flip ? 2 * scratch_items : 0);
+        uint32_t* oi = ok + scratch_items;
+        if (!in_key)
+            hipLaunchKernelGGL(select_stage_kernel<true>, dim3(blocks), dim3(kSelThreads), 0, s, pred, nullptr,
+                               nullptr, count, k, ok, oi);
+        else
+            hipLaunchKernelGGL(select_stage_kernel<false>, dim3(blocks), dim3(kSelThreads), 0, s, nullptr, in_key,
+                               in_idx, count, k, ok, oi);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        in_key = ok;
+        in_idx = oi;
+        count = blocks * k;
+        flip ^= 1;
+    }
+    // four items per thread when they fit, sixteen otherwise
+#define NBT_FINAL(FP, RR)                                                                                \
+    hipLaunchKernelGGL((select_final_kernel<FP, RR>), dim3(1), dim3(kSelThreads), 0, s, FP ? pred : nullptr, \
+                       in_key, in_idx, count, k, poses, cand, cand_poses)
+    if (!in_key) {
+        if (count <= 4 * kSelThreads) NBT_FINAL(true, 4); else NBT_FINAL(true, 16);
+    } else {
+        if (count <= 4 * kSelThreads) NBT_FINAL(false, 4); else NBT_FINAL(false, 16);
+    }
+#undef NBT_FINAL
     return hipGetLastError();
 }
 
@@ -519,15 +1029,9 @@ hipError_t launch_topk(const float* vals, uint32_t n, uint32_t k, unsigned long 
     return final(topk_final_kernel<4>, 4);
 }
 
-hipError_t launch_gather_poses(const float* poses, const uint32_t* idx, uint32_t k, float* out,
-                               hipStream_t s) {
-    hipLaunchKernelGGL(gather_poses_kernel, dim3((k * 12 + 255) / 256), dim3(256), 0, s, poses, idx, k, out);
-    return hipGetLastError();
-}
-
 hipError_t launch_final_select(const float* ig_exact, const uint32_t* cand, uint32_t kr, uint32_t k,
                                uint32_t* idx_out, float* ig_out, hipStream_t s) {
-    hipLaunchKernelGGL(final_select_kernel, dim3(1), dim3(1024), 0, s, ig_exact, cand, kr, k, idx_out, ig_out);
+    hipLaunchKernelGGL(final_select_kernel, dim3(1), dim3(kMaxRescore), 0, s, ig_exact, cand, kr, k, idx_out, ig_out);
     return hipGetLastError();
 }
 

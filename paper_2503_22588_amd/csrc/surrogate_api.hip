@@ -31,13 +31,16 @@ struct nbt_ig_surrogate {
     float* b2 = nullptr;
     float* w3 = nullptr;
     // per-call buffers
-    __bf16* patch = nullptr;
-    __bf16* act[4] = {nullptr, nullptr, nullptr, nullptr};
+    __bf16* act2 = nullptr;      // conv2 output, channel-last
+    __bf16* act3 = nullptr;      // conv3 output, channel-last
+    __bf16* feat = nullptr;      // trunk features
     float* c = nullptr;
-    float* pred = nullptr;
-    size_t pred_cap = 0;
-    unsigned long long* keep = nullptr;
-    size_t keep_cap = 0;
+    float* pred = nullptr;       // predictions of a selection (grown stream-ordered)
+    size_t pred_bytes = 0;
+    bool pred_async = false;
+    uint32_t* sel = nullptr;     // selection stages' keys and indices (grown stream-ordered)
+    size_t sel_bytes = 0;
+    bool sel_async = false;
     uint32_t* cand = nullptr;
     float* cand_poses = nullptr;
     float* cand_ig = nullptr;
@@ -63,23 +66,36 @@ hipError_t upload(nbt_ig_surrogate* s, T** p, const std::vector<T>& host) {
 int run_trunk(nbt_ig_surrogate* s, const nbt_ig_map* map, const float poi[3], float* patch_f32,
               hipStream_t st) {
     const double vox = map->voxel;
-    int f = (int)std::floor((double)s->extent / (kGrid * vox) + 0.5);
-    if (f < 1) f = 1;
+    const double fd = std::floor((double)s->extent / (kGrid * vox) + 0.5);
+    if (!(fd <= 4096.0)) return fail(NBT_IG_EUNSUPPORTED, "patch extent of more than 4096 voxels per cell");
+    const int f = fd < 1.0 ? 1 : (int)fd;
     int i0[3];
     for (int a = 0; a < 3; ++a) {
         const double q = std::floor(((double)poi[a] - (double)map->origin[a]) / vox + 0.5);
         if (!(std::fabs(q) < 1e9)) return fail(NBT_IG_EINVAL, "PoI is not finite or too far from the map");
         i0[a] = (int)q - (kGrid / 2) * f;
     }
-    hipError_t e = launch_patch(map->dm, f, i0, s->patch, patch_f32, st);
-    const __bf16* in = s->patch;
-    int size = kGrid;
-    for (int l = 0; l < 4 && e == hipSuccess; ++l) {
-        e = launch_conv(in, kConvIn[l], size, s->conv_w[l], s->conv_b[l], kConvOut[l], s->kpad[l], s->act[l], st);
-        in = s->act[l];
-        size /= 2;
+    hipError_t e = hipSuccess;
+    if (patch_f32) e = launch_patch(map->dm, f, i0, nullptr, patch_f32, st);
+    if (e == hipSuccess) {
+        TrunkArgs a;
+        a.m = map->dm;
+        a.f = f;
+        a.i0x = i0[0];
+        a.i0y = i0[1];
+        a.i0z = i0[2];
+        for (int l = 0; l < 4; ++l) {
+            a.w[l] = s->conv_w[l];
+            a.b[l] = s->conv_b[l];
+        }
+        a.w1f = s->w1f;
+        a.fb1 = s->b1;
+        a.act2 = s->act2;
+        a.act3 = s->act3;
+        a.feat = s->feat;
+        a.c = s->c;
+        e = launch_trunk(a, st);
     }
-    if (e == hipSuccess) e = launch_fc1_feature(s->act[3], s->w1f, s->b1, s->c, st);
     if (e != hipSuccess) return hip_fail(e, "surrogate trunk");
     return NBT_IG_OK;
 }
@@ -127,11 +143,17 @@ int nbt_ig_surrogate_create(nbt_ig_ctx* ctx, const void* weights, size_t nbytes,
     hipError_t e = hipSuccess;
     size_t off = 0;
     for (int l = 0; l < 4 && e == hipSuccess; ++l) {
+        // blob order [cout][cin][tap]; library order k = ci*27 + tap for conv1,
+        // k = tap*cin + ci for the others (see TrunkArgs)
         const int ci = kConvIn[l], co = kConvOut[l], K = ci * 27;
-        s->kpad[l] = (K + 31) / 32 * 32;
+        s->kpad[l] = conv_kpad(l);
         std::vector<uint16_t> w((size_t)co * s->kpad[l], 0);
         for (int n = 0; n < co; ++n)
-            for (int k = 0; k < K; ++k) w[(size_t)n * s->kpad[l] + k] = to_bf16(p[off + (size_t)n * K + k]);
+            for (int c = 0; c < ci; ++c)
+                for (int tap = 0; tap < 27; ++tap) {
+                    const int k = l == 0 ? c * 27 + tap : tap * ci + c;
+                    w[(size_t)n * s->kpad[l] + k] = to_bf16(p[off + (size_t)n * K + (size_t)c * 27 + tap]);
+                }
         off += (size_t)co * K;
         std::vector<float> bias(p.begin() + off, p.begin() + off + co);
         off += co;
@@ -163,10 +185,9 @@ int nbt_ig_surrogate_create(nbt_ig_ctx* ctx, const void* weights, size_t nbytes,
         if (e == hipSuccess) e = upload(s, &s->b2, b2);
         if (e == hipSuccess) e = upload(s, &s->w3, w3);
     }
-    if (e == hipSuccess) e = dalloc(s, &s->patch, 2 * (size_t)kPatchCells);
-    int size = kGrid / 2;
-    for (int l = 0; l < 4 && e == hipSuccess; ++l, size /= 2)
-        e = dalloc(s, &s->act[l], (size_t)kConvOut[l] * size * size * size);
+    if (e == hipSuccess) e = dalloc(s, &s->act2, (size_t)kConvOut[1] * 8 * 8 * 8);
+    if (e == hipSuccess) e = dalloc(s, &s->act3, (size_t)kConvOut[2] * 4 * 4 * 4);
+    if (e == hipSuccess) e = dalloc(s, &s->feat, kFeat);
     if (e == hipSuccess) e = dalloc(s, &s->c, kHidden);
     if (e == hipSuccess) e = dalloc(s, &s->cand, kMaxRescore);
     if (e == hipSuccess) e = dalloc(s, &s->cand_poses, 12 * (size_t)kMaxRescore);
@@ -183,8 +204,9 @@ void nbt_ig_surrogate_destroy(nbt_ig_surrogate* s) {
     if (!s) return;
     DeviceGuard g(s->ctx->device);
     for (void* p : s->owned) (void)hipFree(p);
-    if (s->pred) (void)hipFree(s->pred);
-    if (s->keep) (void)hipFree(s->keep);
+    release_buffer(s->pred, s->pred_async, nullptr);
+    release_buffer(s->sel, s->sel_async, nullptr);
+    if (s->pred_async || s->sel_async) (void)hipStreamSynchronize(nullptr);
     delete s;
 }
 
@@ -220,26 +242,35 @@ int nbt_ig_surrogate_select(nbt_ig_surrogate* s, const nbt_ig_map* map, const nb
     DeviceGuard g(s->ctx->device);
     if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", s->ctx->device);
     hipStream_t st = (hipStream_t)stream;
-    const size_t need = topk_scratch_keys(n, k_rescore);
+    if (!poses) return fail(NBT_IG_EINVAL, "poses is NULL");
+    if (int rc = check_map(map)) return rc;
+    if (map->ctx != s->ctx) return fail(NBT_IG_EINVAL, "map and surrogate belong to different contexts");
+    if (int rc = check_poi(poi)) return rc;
     {
         std::lock_guard<std::mutex> lk(s->ctx->mu);
-        hipError_t e = hipSuccess;
-        if (s->pred_cap < n) {
-            if (s->pred) { (void)hipStreamSynchronize(st); (void)hipFree(s->pred); s->pred = nullptr; }
-            e = hipMalloc(&s->pred, (size_t)n * sizeof(float));
-            s->pred_cap = e == hipSuccess ? n : 0;
+        void* q = s->pred;
+        if (int rc = grow_buffer(&q, &s->pred_bytes, &s->pred_async, (size_t)n * sizeof(float), st,
+                                 "surrogate predictions"))
+            return rc;
+        s->pred = static_cast<float*>(q);
+        const size_t items = select_scratch_items(n, k_rescore);
+        if (items) {
+            q = s->sel;
+            if (int rc = grow_buffer(&q, &s->sel_bytes, &s->sel_async, 4 * items * sizeof(uint32_t), st,
+                                     "surrogate selection stages"))
+                return rc;
+            s->sel = static_cast<uint32_t*>(q);
         }
-        if (e == hipSuccess && s->keep_cap < need) {
-            if (s->keep) { (void)hipStreamSynchronize(st); (void)hipFree(s->keep); s->keep = nullptr; }
-            e = hipMalloc(&s->keep, need * sizeof(unsigned long long));
-            s->keep_cap = e == hipSuccess ? need : 0;
-        }
-        if (e != hipSuccess) return hip_fail(e, "surrogate scratch");
     }
-    if (int rc = nbt_ig_surrogate_predict(s, map, poi, poses, n, s->pred, stream)) return rc;
-    hipError_t e = launch_topk(s->pred, n, k_rescore, s->keep, s->cand, st);
-    if (e == hipSuccess) e = launch_gather_poses(poses, s->cand, k_rescore, s->cand_poses, st);
-    if (e != hipSuccess) return hip_fail(e, "surrogate top-k");
+    // trunk, MLP, selection of the k_rescore best as a set with their poses,
+    // exact rescoring, final pick
+    if (int rc = run_trunk(s, map, poi, nullptr, st)) return rc;
+    hipError_t e = launch_mlp(poses, n, poi, s->dist_mean, s->dist_scale, s->c, s->w1d, s->w2, s->b2, s->w3,
+                              s->b3, s->out_scale, s->pred, s->ctx->cu_count, st);
+    if (e == hipSuccess)
+        e = launch_select(s->pred, n, k_rescore, poses, s->sel, select_scratch_items(n, k_rescore), s->cand,
+                          s->cand_poses, st);
+    if (e != hipSuccess) return hip_fail(e, "surrogate mlp and selection");
     if (int rc = nbt_ig_eval_viewpoints(map, cam, s->cand_poses, k_rescore, s->cand_ig, nullptr, stream))
         return rc;
     e = launch_final_select(s->cand_ig, s->cand, k_rescore, k, idx_out, ig_out, st);
@@ -257,7 +288,7 @@ int nbt_ig_surrogate_features(nbt_ig_surrogate* s, const nbt_ig_map* map, const 
     hipStream_t st = (hipStream_t)stream;
     if (int rc = run_trunk(s, map, poi, patch_out, st)) return rc;
     if (features_out) {
-        hipError_t e = launch_bf16_to_f32(s->act[3], kFeat, features_out, st);
+        hipError_t e = launch_bf16_to_f32(s->feat, kFeat, features_out, st);
         if (e != hipSuccess) return hip_fail(e, "surrogate features");
     }
     return NBT_IG_OK;

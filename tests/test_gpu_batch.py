@@ -164,7 +164,8 @@ def test_batch_launch_shapes_and_autotune(nbt, ctx, uneven):
 
 
 def test_cfg3_full_size(nbt, ctx):
-    """Config 3 at its real size: 64 maps of 64..256^3 voxels, ~31k perspectives."""
+    """Config 3 at its real size: 64 maps of 64..256^3 voxels, ~31k perspectives; the batch equals
+    the single-map path bit for bit on all of them, and the oracle on four perspectives of every map."""
     import torch
     w = make_config(3)
     cam = w.camera
@@ -182,9 +183,10 @@ def test_cfg3_full_size(nbt, ctx):
     ig, st = ig.cpu().numpy(), st.cpu().numpy()
     ig_single, st_single = _single(nbt, maps, cam, w.poses)
     assert np.array_equal(st, st_single) and np.array_equal(ig, ig_single)
+    # every map against the oracle: four perspectives each (its first and last, two at random)
     rng = np.random.default_rng(33)
-    for k in rng.choice(len(w.maps), size=3, replace=False):
-        pick = rng.choice(counts[k], size=min(3, counts[k]), replace=False)
+    for k in range(len(w.maps)):
+        pick = np.unique(np.concatenate([[0, counts[k] - 1], rng.choice(counts[k], size=2)]))
         a, c = oracle.eval_viewpoints(w.maps[k], cam, w.poses[k][pick])
         g = offsets[k] + pick
         assert np.array_equal(st[g].view(np.uint64), c)
