@@ -356,15 +356,33 @@ def extra_batch(nbt, ctx, reps, ceilings=None):
     return res
 
 
-def extra_surrogate(nbt, ctx, n_maps=16, n_cand=65536, k_rescores=(64, 256, 1024), k=10, target=0.95):
-    """Surrogate-pruned selection vs plain raycasting on held-out config-1-family maps, at
-    several rescoring budgets; the headline operating point is the smallest budget whose
-    top-10 agreement with exact IG reaches `target`."""
+def _held_out_map(family, i):
+    """(P, voxel, origin, poi, shell, camera, seed) of held-out map i of a surrogate family (seeds
+    outside the training ranges of paper_2503_22588_amd/train_surrogate.py)."""
+    import numpy as np
+    from workloads import scene_spheres, scene_tabletop
+    from workloads.configs import CAM1, CAM2
+    if family == "cfg1":
+        seed = 22588 + 5000 + 100000 + i
+        sc = scene_spheres(n=64, voxel=0.05, n_spheres=10 + seed % 31, seed=seed)
+        return sc.P, sc.voxel, sc.origin, np.asarray(sc.poi, np.float32), (0.4, 1.3), CAM1, seed
+    seed = 22588 + 6000 + 100000 + i
+    sc = scene_tabletop(n=256, voxel=0.02, n_objects=200, seed=seed)
+    tops = sc.extra["object_tops"]
+    poi = np.asarray(tops[np.random.default_rng(seed + 77).choice(len(tops), size=4, replace=False)[0]], np.float32)
+    return sc.P, sc.voxel, sc.origin, poi, (0.5, 1.2), CAM2, seed
+
+
+def extra_surrogate(nbt, ctx, family="cfg1", n_maps=16, n_cand=65536, k_rescores=(64, 256, 1024), k=10,
+                    target=0.95):
+    """Surrogate-pruned selection vs plain raycasting on held-out maps of one scene family
+    (cfg1: 64^3 sphere maps, cfg2: 256^3 table-top maps), at several rescoring budgets; the
+    headline operating point is the smallest budget whose top-10 agreement with exact IG
+    reaches `target`."""
     import numpy as np
     import torch
-    from workloads import poses_shell, scene_spheres
-    from workloads.configs import CAM1
-    path = os.path.join(ROOT, "paper_2503_22588_amd", "weights", "surrogate_cfg1.nbts")
+    from workloads import poses_shell
+    path = os.path.join(ROOT, "paper_2503_22588_amd", "weights", f"surrogate_{family}.nbts")
     if not os.path.exists(path):
         return {"skipped": f"no trained weights at {os.path.relpath(path, ROOT)}"}
     blob = open(path, "rb").read()
@@ -373,14 +391,13 @@ def extra_surrogate(nbt, ctx, n_maps=16, n_cand=65536, k_rescores=(64, 256, 1024
     t_plain, nmae = [], []
     per = {kr: {"agree": [], "ratio": [], "ms": []} for kr in k_rescores}
     for i in range(n_maps):
-        seed = 22588 + 5000 + 100000 + i                     # held out from training
-        sc = scene_spheres(n=64, voxel=0.05, n_spheres=10 + seed % 31, seed=seed)
-        poi = np.asarray(sc.poi, np.float32)
-        m = nbt.Map(ctx, sc.P, sc.voxel, sc.origin)
-        m.set_layout(nbt.LAYOUT_LINEAR)     # 5 cm map, dense rays: the linear order is faster
-        dp = torch.from_numpy(poses_shell(poi.astype(np.float64), 0.4, 1.3, n_cand, seed + 500)).cuda()
+        P, vox, origin, poi, shell, CAM, seed = _held_out_map(family, i)
+        m = nbt.Map(ctx, P, vox, origin)
+        if family == "cfg1":
+            m.set_layout(nbt.LAYOUT_LINEAR)     # 5 cm map, dense rays: the linear order is faster
+        dp = torch.from_numpy(poses_shell(poi.astype(np.float64), shell[0], shell[1], n_cand, seed + 500)).cuda()
         ig = torch.empty(n_cand, device="cuda")
-        t_plain.append(_timed(lambda: nbt.eval_viewpoints(m, CAM1, dp, ig_out=ig, want_steps=False), 3, stream))
+        t_plain.append(_timed(lambda: nbt.eval_viewpoints(m, CAM, dp, ig_out=ig, want_steps=False), 3, stream))
         ex = ig.cpu().numpy()
         top = set(np.lexsort((np.arange(n_cand), -ex))[:k].tolist())
         sel_idx = torch.empty(k, dtype=torch.int32, device="cuda")
@@ -389,7 +406,7 @@ def extra_surrogate(nbt, ctx, n_maps=16, n_cand=65536, k_rescores=(64, 256, 1024
             out = {}
 
             def sel():
-                out["r"] = sur.select(m, CAM1, poi, dp, k_rescore=kr, k=k, idx_out=sel_idx, ig_out=sel_ig)
+                out["r"] = sur.select(m, CAM, poi, dp, k_rescore=kr, k=k, idx_out=sel_idx, ig_out=sel_ig)
 
             per[kr]["ms"].append(_timed(sel, 5, stream))
             per[kr]["agree"].append(len(top & set(out["r"][0].cpu().numpy().tolist())) / k)
@@ -409,8 +426,11 @@ def extra_surrogate(nbt, ctx, n_maps=16, n_cand=65536, k_rescores=(64, 256, 1024
                        "worst_best_ig_ratio": float(np.min(per[kr]["ratio"]))})
     ok = [p for p in points if p["top10_agreement"] >= target]
     head = ok[0] if ok else points[-1]
-    return {"workload": f"{n_maps} held-out 64^3 sphere maps, {n_cand} candidates in the 0.4-1.3 m shell, "
-                        f"64x48 rays; top-k_rescore rescored exactly, top-{k} kept",
+    desc = {"cfg1": f"{n_maps} held-out 64^3 sphere maps (5 cm), {n_cand} candidates in the 0.4-1.3 m shell, "
+                    f"64x48 rays",
+            "cfg2": f"{n_maps} held-out 256^3 table-top maps (2 cm, f = 5 crop), {n_cand} candidates in the "
+                    f"0.5-1.2 m shell around an object top, 160x120 rays"}[family]
+    return {"workload": f"{desc}; top-k_rescore rescored exactly, top-{k} kept",
             "plain_ms": tp, "plain_evals_per_s": n_cand / (tp * 1e-3),
             "k_rescore": head["k_rescore"], "surrogate_ms": head["surrogate_ms"],
             "surrogate_evals_per_s": head["surrogate_evals_per_s"], "speedup": head["speedup"],
@@ -485,7 +505,8 @@ def main():
                     help="skip the trajectory and batched measurements")
     ap.add_argument("--no-ceilings", action="store_true",
                     help="skip the memory-probe ceilings (stream, gather) and the fractions against them")
-    ap.add_argument("--only", choices=("trajectories", "batched", "surrogate", "insert", "ceilings"), default=None,
+    ap.add_argument("--only", choices=("trajectories", "batched", "surrogate", "surrogate_tabletop", "insert",
+                                       "ceilings"), default=None,
                     help="only run one of the extra workloads (one JSON object)")
     ap.add_argument("--e1-sweep", action="store_true",
                     help="only run the N_P x s_G runtime sweep at 1 cm voxels (one JSON object per line)")
@@ -536,6 +557,7 @@ def main():
         run = {"trajectories": lambda: extra_trajectories(nbt, cx, reps=3),
                "batched": lambda: extra_batch(nbt, cx, reps=5),
                "surrogate": lambda: extra_surrogate(nbt, cx),
+               "surrogate_tabletop": lambda: extra_surrogate(nbt, cx, family="cfg2", n_maps=4),
                "insert": lambda: extra_insert(nbt, cx, reps=5),
                "ceilings": lambda: measure_ceilings(nbt, cx)}[args.only]
         print(json.dumps({args.only: run()}), flush=True)
@@ -679,6 +701,8 @@ def main():
         result["batched"] = extra_batch(nbt, cx, reps=5, ceilings=ceilings)
         _log("measuring the surrogate (config 5) ...")
         result["surrogate"] = extra_surrogate(nbt, cx)
+        _log("measuring the surrogate on table-top maps (config 5, config-2 family) ...")
+        result["surrogate_tabletop"] = extra_surrogate(nbt, cx, family="cfg2", n_maps=4)
         _log("measuring the map update by depth insertion ...")
         result["insert"] = extra_insert(nbt, cx, reps=5)
         _log("measuring the runtime sweep at 1 cm voxels (compact) ...")

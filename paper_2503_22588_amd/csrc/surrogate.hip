@@ -405,6 +405,20 @@ __global__ __launch_bounds__(kMlpWaves * 64) void mlp_kernel(const float* __rest
     float* sc = sw1d + kW1dWords;
     float* sb2 = sc + kHidden;
     float* sw3 = sb2 + kHidden;
+    const int lane = threadIdx.x & 63;
+    const int row = lane & 15, kq = lane >> 4;
+    const uint32_t ngroup = (n + 31) / 32;
+    const uint32_t wave_global = blockIdx.x * kMlpWaves + (threadIdx.x >> 6);
+    const uint32_t waves = gridDim.x * kMlpWaves;
+    // this wave's first camera centres, requested before the LDS fill so that
+    // their latency passes during it
+    float cen[2][3];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const uint32_t p = wave_global * 32 + i * 16 + row;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) cen[i][a] = (wave_global < ngroup && p < n) ? poses[12 * (size_t)p + 9 + a] : 0.0f;
+    }
     for (int i = threadIdx.x; i < kHidden * kHidden / 8; i += blockDim.x) {
         const int r = (i * 8) / kHidden, k = (i * 8) % kHidden;
         *reinterpret_cast<bf16x8_t*>(sw2 + r * kW2Stride + k) =
@@ -418,11 +432,6 @@ __global__ __launch_bounds__(kMlpWaves * 64) void mlp_kernel(const float* __rest
     }
     __syncthreads();
 
-    const int lane = threadIdx.x & 63;
-    const int row = lane & 15, kq = lane >> 4;
-    const uint32_t ngroup = (n + 31) / 32;
-    const uint32_t wave_global = blockIdx.x * kMlpWaves + (threadIdx.x >> 6);
-    const uint32_t waves = gridDim.x * kMlpWaves;
     for (uint32_t g = wave_global; g < ngroup; g += waves) {
         float u0[2], u1[2], u2[2], dn[2];
 #pragma unroll
@@ -430,15 +439,24 @@ __global__ __launch_bounds__(kMlpWaves * 64) void mlp_kernel(const float* __rest
             const uint32_t p = g * 32 + i * 16 + row;
             u0[i] = u1[i] = u2[i] = dn[i] = 0.0f;
             if (p < n) {
-                const float vx = poses[12 * (size_t)p + 9] - px;
-                const float vy = poses[12 * (size_t)p + 10] - py;
-                const float vz = poses[12 * (size_t)p + 11] - pz;
+                const float vx = cen[i][0] - px;
+                const float vy = cen[i][1] - py;
+                const float vz = cen[i][2] - pz;
                 const float d = sqrtf(vx * vx + vy * vy + vz * vz);
                 const float inv = d > 0.0f ? 1.0f / d : 0.0f;
                 u0[i] = vx * inv;
                 u1[i] = vy * inv;
                 u2[i] = vz * inv;
                 dn[i] = (d - dist_mean) / dist_scale;
+            }
+        }
+        {
+            const uint32_t g2 = g + waves;            // the next group's centres, if any
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const uint32_t p = g2 * 32 + i * 16 + row;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) cen[i][a] = (g2 < ngroup && p < n) ? poses[12 * (size_t)p + 9 + a] : 0.0f;
             }
         }
         // output-stationary: the 16 column tiles of h2 stay in registers while

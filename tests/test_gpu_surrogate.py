@@ -254,6 +254,44 @@ def test_trained_weights_parity_and_quality(nbt, ctx):
     assert np.mean(agree) >= 0.6, agree
 
 
+TRAINED_TABLETOP = __import__("os").path.join(__import__("os").path.dirname(__file__), "..",
+                                              "paper_2503_22588_amd", "weights", "surrogate_cfg2.nbts")
+
+
+def test_trained_tabletop_weights_parity_and_quality(nbt, ctx):
+    """The shipped table-top weights (256^3 maps at 2 cm, a 160^3 crop pooled 5x, the 160x120
+    camera): predictions match the float64 reference forward (BF16 rounding mirrored, and not)
+    to the BF16 bar, and on a map held out from training the pruned selection (256 of 16384
+    candidates rescored exactly) picks a view within a few percent of the exhaustive best."""
+    import torch
+    from workloads import scene_tabletop
+    from workloads.configs import CAM2
+    blob = open(TRAINED_TABLETOP, "rb").read()
+    params, meta = S.unpack_weights(blob)
+    sur = nbt.Surrogate(ctx, blob)
+    seed = 22588 + 6000 + 200000                     # outside the training and bench seeds
+    sc = scene_tabletop(n=256, voxel=0.02, n_objects=200, seed=seed)
+    poi = np.asarray(sc.extra["object_tops"][5], np.float32)
+    _note(f"trained table-top surrogate, map seed {seed}")
+    m = nbt.Map(ctx, sc.P, sc.voxel, sc.origin)
+    poses = poses_shell(poi.astype(np.float64), 0.5, 1.2, 16384, seed=seed + 500)
+    dp = _dev(poses)
+    pred = sur.predict(m, poi, dp)
+    exact, _ = nbt.eval_viewpoints(m, CAM2, dp)
+    idx, ig = sur.select(m, CAM2, poi, dp, k_rescore=256, k=10)
+    torch.cuda.synchronize()
+    patch = S.extract_patch(sc.P, sc.voxel, sc.origin, poi, meta["extent"])
+    got = pred.cpu().numpy()[:2000].astype(np.float64)
+    for emulate in (True, False):
+        ref = S.head(params, meta, S.trunk(params, patch, emulate), poses[:2000], poi, emulate)
+        assert np.max(np.abs(got - ref)) <= 2e-2 * np.max(np.abs(ref)), emulate
+    ex = exact.cpu().numpy().astype(np.float64)
+    ratio = float(ig.cpu().numpy()[0]) / ex.max()
+    assert ratio >= 0.9, ratio
+    m.close()
+    sur.close()
+
+
 def test_select_repeats_are_identical(nbt, ctx, setup):
     """Repeated selections into the same output buffers, with other work on the surrogate's and
     the context's buffers and synchronisations in between, give identical bits; a smaller k
