@@ -422,7 +422,7 @@ int nbt_ig_autotune_map(nbt_ig_map* map, const nbt_ig_camera* cam, const float* 
  * candidate perspective from (a) a 32^3 x 2 patch around the PoI holding the
  * fraction of occupied and of unknown voxels per cell and (b) the candidate's
  * unit direction and distance from the PoI; it prunes candidates so that only
- * the best few are raycast exactly (Sec. III's g_P stays the judge).
+ * the best few are raycast exactly (Sec. III's g_P decides).
  * Network: 4 conv3d layers (3^3, stride 2, ReLU; 2-16-32-64-64 channels,
  * 32^3 -> 2^3) -> 512 features; MLP 516 -> 256 -> 256 -> 1 (ReLU).  Inference
  * runs in BF16 on MFMA with FP32 accumulation; the pose-independent part of
@@ -467,7 +467,8 @@ int nbt_ig_extract_patch(const nbt_ig_map* map, const float poi[3], float extent
  * The k largest of n values (DEVICE float32, e.g. the per-perspective IG of
  * nbt_ig_eval_viewpoints: k = 1 is the NBV of an ID), best first, ties to
  * the lower index; idx_out DEVICE uint32 [k], val_out DEVICE float32 [k] (may
- * be NULL).  NaN ranks last.  1 <= k <= 1024, k <= n <= 2^22. */
+ * be NULL).  NaN ranks last; -0 and +0 are equal values.  1 <= k <= 1024,
+ * k <= n <= 2^22. */
 int nbt_ig_top_k(nbt_ig_ctx* ctx, const float* values, uint32_t n, uint32_t k, uint32_t* idx_out,
                  float* val_out, void* stream);
 

@@ -1,7 +1,6 @@
 // surrogate.hip -- learned IG surrogate: patch, conv3d trunk and MLP on BF16
-// MFMA (FP32 accumulation), radix selection of the candidates to rescore and
-// the final pick after exact rescoring; the bitonic top-k of the generic
-// selection call.
+// MFMA (FP32 accumulation), radix selection of the candidates to rescore (also
+// the generic top-k) and the final pick after exact rescoring.
 //
 // Matrix fragments follow v_mfma_f32_16x16x32_bf16 (gfx950): for lane l,
 // A (16 x 32) row l%16 holds k = (l/16)*8 .. +7, B (32 x 16) column l%16 holds
@@ -367,7 +366,7 @@ __global__ __launch_bounds__(256) void trunk_fc1_kernel(TrunkArgs p) {
 }
 
 // ---------------------------------------------------------------- MLP ------
-// Per pose: h1 = ReLU(c + W1d [u, dn]) (FP32, stored BF16), h2 = ReLU(W2 h1 +
+// Per pose: h1 = ReLU(c + W1d [u, dn]) (FP32 MFMA, stored BF16), h2 = ReLU(W2 h1 +
 // b2) on MFMA with W2 staged in LDS (rows padded to 264 halves so the 16
 // lanes reading one k-slice of 16 rows hit distinct banks), y = out_scale *
 // (W3 . h2 + b3).  One workgroup of 8 waves per CU shares the LDS copy of W2
@@ -464,23 +463,27 @@ __global__ __launch_bounds__(kMlpWaves * 64) void mlp_kernel(const float* __rest
         f32x4_t acc[2][kHidden / 16];
 #pragma unroll
         for (int nt = 0; nt < kHidden / 16; ++nt) acc[0][nt] = acc[1][nt] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 1
+        // this lane's input feature (u0, u1, u2 or dn by lane group) of pose
+        // `row` of each tile: the B operand of the h1 products below
+        const float feat_in[2] = {kq == 0 ? u0[0] : kq == 1 ? u1[0] : kq == 2 ? u2[0] : dn[0],
+                                  kq == 0 ? u0[1] : kq == 1 ? u1[1] : kq == 2 ? u2[1] : dn[1]};
+#pragma unroll 2
         for (int ks = 0; ks < kHidden / 32; ++ks) {
+            // h1 = c + W1d [u, dn] on the FP32 MFMA, transposed (neurons x poses):
+            // block j of 16 neurons gives this lane neurons ks*32 + 16j + 4*kq + r
+            // (r = 0..3) of pose `row`, which become elements 4j + r of its A
+            // fragment (W2's columns are stored in the same order)
             bf16x8_t a[2];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int k = ks * 32 + kq * 8 + e;
-                const float4 wd = *reinterpret_cast<const float4*>(sw1d + w1d_slot(k));
-                const float ck = sc[k];
+            for (int j = 0; j < 2; ++j) {
+                const int nb = ks * 32 + 16 * j;
+                const float wa = sw1d[w1d_slot(nb + row) + kq];
+                const f32x4_t cc = {sc[nb + 4 * kq], sc[nb + 4 * kq + 1], sc[nb + 4 * kq + 2], sc[nb + 4 * kq + 3]};
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
-                    // fused multiply-adds: one rounding per term (the library is
-                    // otherwise built without contraction)
-                    float h = __builtin_fmaf(wd.x, u0[i], ck);
-                    h = __builtin_fmaf(wd.y, u1[i], h);
-                    h = __builtin_fmaf(wd.z, u2[i], h);
-                    h = __builtin_fmaf(wd.w, dn[i], h);
-                    a[i][e] = (__bf16)(h > 0.0f ? h : 0.0f);
+                    const f32x4_t h = __builtin_amdgcn_mfma_f32_16x16x4f32(wa, feat_in[i], cc, 0, 0, 0);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) a[i][4 * j + r] = (__bf16)(h[r] > 0.0f ? h[r] : 0.0f);
                 }
             }
             const __bf16* bk = sw2 + row * kW2Stride + ks * 32 + kq * 8;
@@ -693,7 +696,7 @@ __global__ __launch_bounds__(kSelThreads) void select_stage_kernel(const float* 
 }
 
 // The last stage (one workgroup, count <= 1024 R): the k best become the
-// candidates, with their poses.
+// candidates, with their poses when `poses` is given.
 template <bool FROM_PRED, int R>
 __global__ __launch_bounds__(kSelThreads) void select_final_kernel(const float* __restrict__ pred,
                                                                    const uint32_t* __restrict__ in_key,
@@ -726,7 +729,8 @@ __global__ __launch_bounds__(kSelThreads) void select_final_kernel(const float* 
         const uint32_t p = atomicAdd(&s_count, 1u);
         if (p < k) {
             cand[p] = ii;
-            for (int e = 0; e < 12; ++e) cand_poses[12 * (size_t)p + e] = poses[12 * (size_t)ii + e];
+            if (poses)
+                for (int e = 0; e < 12; ++e) cand_poses[12 * (size_t)p + e] = poses[12 * (size_t)ii + e];
         }
     });
 }
@@ -738,154 +742,23 @@ __device__ __forceinline__ unsigned long long rank_key(float v, uint32_t idx) {
     return ((unsigned long long)mono_key(v) << 32) | (unsigned long long)(0xFFFFFFFFu - idx);
 }
 
-// Bitonic sort, descending, of N = 1024 R keys held by a 1024-thread block,
-// thread t holding keys t R .. t R + R - 1 (index i = t R + r).  A compare-
-// exchange whose partner i ^ stride lies in the same thread runs on registers,
-// one in the same wave on lane shuffles, and only strides of 64 R and more go
-// through LDS (lds: N keys), so a 4096-key sort takes 10 barrier stages
-// instead of 78.  Same network, same result as the all-LDS formulation.
-template <int R>
-__device__ __forceinline__ void cmpx_reg(unsigned long long (&key)[R], int t, int size, int stride) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int r2 = r ^ stride;
-        if (r2 > r) {
-            const int i = t * R + r;
-            const bool desc = (i & size) == 0;
-            const unsigned long long a = key[r], b = key[r2];
-            if ((a < b) == desc) {
-                key[r] = b;
-                key[r2] = a;
-            }
-        }
-    }
-}
-
-// Lane partner t ^ m: quad permutations (DPP, on the vector ALU) for m = 1, 2,
-// a cross-lane permute otherwise.
-__device__ __forceinline__ unsigned long long lane_xor(unsigned long long v, int m) {
-    if (m == 1 || m == 2) {                           // quad_perm [1,0,3,2] / [2,3,0,1]
-        const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
-        const int plo = m == 1 ? __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false)
-                               : __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);
-        const int phi = m == 1 ? __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false)
-                               : __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false);
-        return ((unsigned long long)(uint32_t)phi << 32) | (uint32_t)plo;
-    }
-    return __shfl_xor(v, m);
-}
-
-template <int R>
-__device__ __forceinline__ void cmpx_lane(unsigned long long (&key)[R], int t, int size, int stride) {
-    const int lane_mask = stride / R;                 // partner thread t ^ lane_mask, same wave
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int i = t * R + r;
-        const unsigned long long a = key[r];
-        const unsigned long long b = lane_xor(a, lane_mask);
-        const bool lower = (i & stride) == 0, desc = (i & size) == 0;
-        const bool keep_max = lower == desc;
-        key[r] = keep_max ? (a > b ? a : b) : (a < b ? a : b);
-    }
-}
-
-template <int R>
-__device__ void sort_desc_block(unsigned long long (&key)[R], unsigned long long* lds) {
-    constexpr int N = 1024 * R;
-    const int t = threadIdx.x;
-    for (int size = 2; size <= N; size <<= 1) {
-        int stride = size >> 1;
-        if (stride >= 64 * R) {
-            __syncthreads();                            // previous readers of lds are done
-#pragma unroll
-            for (int r = 0; r < R; ++r) lds[t * R + r] = key[r];
-            for (; stride >= 64 * R; stride >>= 1) {
-                __syncthreads();
-                for (int p = t; p < N / 2; p += 1024) {
-                    const int lo = 2 * p - (p & (stride - 1));
-                    const int hi = lo + stride;
-                    const bool desc = (lo & size) == 0;
-                    const unsigned long long a = lds[lo], b = lds[hi];
-                    if ((a < b) == desc) {
-                        lds[lo] = b;
-                        lds[hi] = a;
-                    }
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < R; ++r) key[r] = lds[t * R + r];
-        }
-        for (; stride >= R; stride >>= 1) cmpx_lane<R>(key, t, size, stride);
-        for (; stride > 0; stride >>= 1) cmpx_reg<R>(key, t, size, stride);
-    }
-}
-
-// Reduction pass: each block ranks 1024 R keys (from values on the first
-// pass, from kept keys afterwards) and keeps its best `keep` (<= 256 R).
-template <bool FROM_VALUES, int R>
-__global__ __launch_bounds__(1024) void topk_pass_kernel(const float* __restrict__ vals,
-                                                         const unsigned long long* __restrict__ keys_in,
-                                                         uint32_t n, uint32_t keep,
-                                                         unsigned long long* __restrict__ keys_out) {
-    __shared__ unsigned long long s[1024 * R];
-    const uint32_t base = blockIdx.x * (1024u * R);
-    unsigned long long key[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t g = base + threadIdx.x * R + r;
-        if constexpr (FROM_VALUES)
-            key[r] = g < n ? rank_key(vals[g], g) : 0ull;
-        else
-            key[r] = g < n ? keys_in[g] : 0ull;
-    }
-    sort_desc_block<R>(key, s);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t i = threadIdx.x * R + r;
-        if (i < keep) keys_out[(size_t)blockIdx.x * keep + i] = key[r];
-    }
-}
-
-// Final pass: one block ranks all remaining keys (count <= 1024 R); writes the
-// k best indices.
-template <int R>
-__global__ __launch_bounds__(1024) void topk_final_kernel(const float* __restrict__ vals,
-                                                          const unsigned long long* __restrict__ keys,
-                                                          uint32_t count, uint32_t k,
-                                                          uint32_t* __restrict__ idx_out) {
-    extern __shared__ unsigned long long s2[];
-    unsigned long long key[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t i = threadIdx.x * R + r;
-        if (vals)
-            key[r] = i < count ? rank_key(vals[i], i) : 0ull;
-        else
-            key[r] = i < count ? keys[i] : 0ull;
-    }
-    sort_desc_block<R>(key, s2);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t i = threadIdx.x * R + r;
-        if (i < k) idx_out[i] = 0xFFFFFFFFu - (uint32_t)(key[r] & 0xFFFFFFFFull);
-    }
-}
-
-// Final pick among the rescored candidates: best exact IG first, ties to the
-// lower candidate index.  Slot j holds candidate cand[j] with IG ig_exact[j];
-// keys are distinct (the candidate index is in the low word), so each slot's
-// rank is the number of larger keys, and the k best write themselves.
-__global__ __launch_bounds__(kMaxRescore) void final_select_kernel(const float* __restrict__ ig_exact,
+// Final pick among the rescored candidates, and the order of a top-k set:
+// slot j holds candidate cand[j] with value vals[j] (vals[cand[j]] when
+// `gather`); the k best come out best first, ties to the lower candidate
+// index.  Keys are distinct (the candidate index is in the low word), so each
+// slot's rank is the number of larger keys, and the k best write themselves.
+__global__ __launch_bounds__(kMaxRescore) void final_select_kernel(const float* __restrict__ vals,
                                                                    const uint32_t* __restrict__ cand,
-                                                                   uint32_t kr, uint32_t k,
+                                                                   uint32_t kr, uint32_t k, int gather,
                                                                    uint32_t* __restrict__ idx_out,
-                                                                   float* __restrict__ ig_out) {
+                                                                   float* __restrict__ val_out) {
     __shared__ __align__(16) unsigned long long s_key[kMaxRescore + 2];
     const uint32_t i = threadIdx.x;
     unsigned long long key = 0ull;
+    float v = 0.0f;
     if (i < kr) {
-        key = rank_key(ig_exact[i], cand[i]);
+        v = gather ? vals[cand[i]] : vals[i];
+        key = rank_key(v, cand[i]);
         s_key[i] = key;
     }
     if (i == 0 && (kr & 1u)) s_key[kr] = 0ull;       // pads an odd count: ranks above no key
@@ -900,7 +773,7 @@ __global__ __launch_bounds__(kMaxRescore) void final_select_kernel(const float* 
     }
     if (rank < k) {
         idx_out[rank] = cand[i];
-        ig_out[rank] = ig_exact[i];
+        if (val_out) val_out[rank] = v;
     }
 }
 
@@ -991,65 +864,10 @@ hipError_t launch_select(const float* pred, uint32_t n, uint32_t k, const float*
     return hipGetLastError();
 }
 
-static uint32_t keep_for(uint32_t k) {
-    uint32_t keep = 1;
-    while (keep < k) keep <<= 1;
-    return keep;
-}
-
-// Keys per pass block: 1024 R with R the smallest of 1, 2, 4 that keeps at
-// most a quarter of them (keep <= 1024), so every pass cuts the count by 4 or
-// more; short blocks sort fast, and there are many of them.
-static int pass_r(uint32_t keep) { return keep <= 256 ? 1 : (keep <= 512 ? 2 : 4); }
-
-size_t topk_scratch_keys(uint32_t n, uint32_t k) {
-    const uint32_t keep = keep_for(k);
-    const uint32_t chunk = 1024u * (uint32_t)pass_r(keep);
-    const size_t first = (size_t)((n + chunk - 1) / chunk) * keep;
-    return 2 * first + 1;
-}
-
-hipError_t launch_topk(const float* vals, uint32_t n, uint32_t k, unsigned long long* scratch,
-                       uint32_t* idx_out, hipStream_t s) {
-    const uint32_t keep = keep_for(k);
-    const int R = pass_r(keep);
-    const uint32_t chunk = 1024u * (uint32_t)R;
-    const unsigned long long* keys = nullptr;
-    uint32_t count = n;
-    const size_t half = (size_t)((n + chunk - 1) / chunk) * keep;
-    int flip = 0;
-    hipError_t e = hipSuccess;
-    while (count > chunk) {
-        const uint32_t blocks = (count + chunk - 1) / chunk;
-        unsigned long long* out = scratch + (flip ? half : 0);
-#define NBT_PASS(FV, RR)                                                                           \
-    hipLaunchKernelGGL((topk_pass_kernel<FV, RR>), dim3(blocks), dim3(1024), 0, s, FV ? vals : nullptr, \
-                       FV ? nullptr : keys, count, keep, out)
-        if (!keys) {
-            if (R == 1) NBT_PASS(true, 1); else if (R == 2) NBT_PASS(true, 2); else NBT_PASS(true, 4);
-        } else {
-            if (R == 1) NBT_PASS(false, 1); else if (R == 2) NBT_PASS(false, 2); else NBT_PASS(false, 4);
-        }
-#undef NBT_PASS
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        keys = out;
-        count = blocks * keep;
-        flip ^= 1;
-    }
-    // one block: 1024 R keys, R = 1, 2 or 4 (count <= chunk)
-    auto final = [&](auto kernel, int RF) -> hipError_t {
-        const size_t lds = (size_t)1024 * RF * sizeof(unsigned long long);     // <= 32 KiB
-        hipLaunchKernelGGL(kernel, dim3(1), dim3(1024), lds, s, keys ? nullptr : vals, keys, count, k, idx_out);
-        return hipGetLastError();
-    };
-    if (count <= 1024) return final(topk_final_kernel<1>, 1);
-    if (count <= 2048) return final(topk_final_kernel<2>, 2);
-    return final(topk_final_kernel<4>, 4);
-}
-
-hipError_t launch_final_select(const float* ig_exact, const uint32_t* cand, uint32_t kr, uint32_t k,
-                               uint32_t* idx_out, float* ig_out, hipStream_t s) {
-    hipLaunchKernelGGL(final_select_kernel, dim3(1), dim3(kMaxRescore), 0, s, ig_exact, cand, kr, k, idx_out, ig_out);
+hipError_t launch_final_select(const float* vals, const uint32_t* cand, uint32_t kr, uint32_t k, bool gather,
+                               uint32_t* idx_out, float* val_out, hipStream_t s) {
+    hipLaunchKernelGGL(final_select_kernel, dim3(1), dim3(kMaxRescore), 0, s, vals, cand, kr, k, gather ? 1 : 0,
+                       idx_out, val_out);
     return hipGetLastError();
 }
 
@@ -1060,17 +878,6 @@ namespace nbt {
 __global__ void bf16_to_f32_kernel(const __bf16* __restrict__ in, uint32_t n, float* __restrict__ out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = (float)in[i];
-}
-
-__global__ void gather_values_kernel(const float* __restrict__ vals, const uint32_t* __restrict__ idx,
-                                     uint32_t k, float* __restrict__ out) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < k) out[i] = vals[idx[i]];
-}
-
-hipError_t launch_gather_values(const float* vals, const uint32_t* idx, uint32_t k, float* out, hipStream_t s) {
-    hipLaunchKernelGGL(gather_values_kernel, dim3((k + 255) / 256), dim3(256), 0, s, vals, idx, k, out);
-    return hipGetLastError();
 }
 
 hipError_t launch_bf16_to_f32(const __bf16* in, uint32_t n, float* out, hipStream_t s) {

@@ -9,7 +9,7 @@ constexpr int kGrid = 32;                          // patch cells per axis
 constexpr int kPatchCells = kGrid * kGrid * kGrid;
 constexpr int kFeat = 512;                         // trunk output: 64 channels x 2^3
 constexpr int kHidden = 256;                       // MLP width
-constexpr int kMaxRescore = 1024;                  // most candidates kept by top-k / rescored exactly
+constexpr int kMaxRescore = 1024;                  // most candidates kept by a selection / rescored exactly
 constexpr uint32_t kMaxCandidates = 1u << 22;      // candidate index fits 22 bits
 constexpr int kConvIn[4] = {2, 16, 32, 64};
 constexpr int kConvOut[4] = {16, 32, 64, 64};
@@ -47,13 +47,11 @@ size_t select_scratch_items(uint32_t n, uint32_t k);
 // The k best predictions (ties to the lower index) as a set, with their poses.
 hipError_t launch_select(const float* pred, uint32_t n, uint32_t k, const float* poses, uint32_t* scratch,
                          size_t scratch_items, uint32_t* cand, float* cand_poses, hipStream_t s);
-// Keys the top-k scratch must hold for n values (two ping-pong halves).
-size_t topk_scratch_keys(uint32_t n, uint32_t k);
-hipError_t launch_topk(const float* vals, uint32_t n, uint32_t k, unsigned long long* scratch,
-                       uint32_t* idx_out, hipStream_t s);
-hipError_t launch_final_select(const float* ig_exact, const uint32_t* cand, uint32_t kr, uint32_t k,
-                               uint32_t* idx_out, float* ig_out, hipStream_t s);
-hipError_t launch_gather_values(const float* vals, const uint32_t* idx, uint32_t k, float* out, hipStream_t s);
+// The k best of kr slots (slot j: candidate cand[j], value vals[j], or
+// vals[cand[j]] when gather), best first, ties to the lower candidate index;
+// val_out may be NULL.  kr <= kMaxRescore.
+hipError_t launch_final_select(const float* vals, const uint32_t* cand, uint32_t kr, uint32_t k, bool gather,
+                               uint32_t* idx_out, float* val_out, hipStream_t s);
 hipError_t launch_bf16_to_f32(const __bf16* in, uint32_t n, float* out, hipStream_t s);
 
 }  // namespace nbt

@@ -170,8 +170,16 @@ int nbt_ig_surrogate_create(nbt_ig_ctx* ctx, const void* weights, size_t nbytes,
         off += (size_t)kHidden * (kFeat + 4);
         std::vector<float> b1(p.begin() + off, p.begin() + off + kHidden);
         off += kHidden;
+        // W2 with its columns in the order the MLP kernel builds h1 in registers:
+        // within each 32-wide k slice, position 8g + e holds neuron 4g + e (e < 4)
+        // or 16 + 4g + e - 4 (e >= 4)
         std::vector<uint16_t> w2((size_t)kHidden * kHidden);
-        for (size_t i = 0; i < w2.size(); ++i) w2[i] = to_bf16(p[off + i]);
+        for (int n = 0; n < kHidden; ++n)
+            for (int j = 0; j < kHidden; ++j) {
+                const int ks = j / 32, g = (j % 32) / 8, e = j % 8;
+                const int src = ks * 32 + (e < 4 ? 4 * g + e : 16 + 4 * g + e - 4);
+                w2[(size_t)n * kHidden + j] = to_bf16(p[off + (size_t)n * kHidden + src]);
+            }
         off += w2.size();
         std::vector<float> b2(p.begin() + off, p.begin() + off + kHidden);
         off += kHidden;
@@ -273,7 +281,7 @@ int nbt_ig_surrogate_select(nbt_ig_surrogate* s, const nbt_ig_map* map, const nb
     if (e != hipSuccess) return hip_fail(e, "surrogate mlp and selection");
     if (int rc = nbt_ig_eval_viewpoints(map, cam, s->cand_poses, k_rescore, s->cand_ig, nullptr, stream))
         return rc;
-    e = launch_final_select(s->cand_ig, s->cand, k_rescore, k, idx_out, ig_out, st);
+    e = launch_final_select(s->cand_ig, s->cand, k_rescore, k, false, idx_out, ig_out, st);
     if (e != hipSuccess) return hip_fail(e, "surrogate select");
     return NBT_IG_OK;
 }
@@ -303,17 +311,19 @@ int nbt_ig_top_k(nbt_ig_ctx* ctx, const float* values, uint32_t n, uint32_t k, u
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", ctx->device);
     hipStream_t st = (hipStream_t)stream;
-    const size_t need = topk_scratch_keys(n, k);
+    // the radix selection's stage buffers, then the chosen set (k indices)
+    const size_t items = select_scratch_items(n, k);
+    const size_t need = (4 * items + k) * sizeof(uint32_t);
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         void* p = ctx->topk_keep;
-        if (int rc = grow_buffer(&p, &ctx->topk_bytes, &ctx->topk_async, need * sizeof(unsigned long long), st,
-                                 "top-k scratch"))
-            return rc;
+        if (int rc = grow_buffer(&p, &ctx->topk_bytes, &ctx->topk_async, need, st, "top-k scratch")) return rc;
         ctx->topk_keep = static_cast<unsigned long long*>(p);
     }
-    hipError_t e = launch_topk(values, n, k, ctx->topk_keep, idx_out, st);
-    if (e == hipSuccess && val_out) e = launch_gather_values(values, idx_out, k, val_out, st);
+    uint32_t* scratch = reinterpret_cast<uint32_t*>(ctx->topk_keep);
+    uint32_t* set = scratch + 4 * items;
+    hipError_t e = launch_select(values, n, k, nullptr, scratch, items, set, nullptr, st);
+    if (e == hipSuccess) e = launch_final_select(values, set, k, k, true, idx_out, val_out, st);
     if (e != hipSuccess) return hip_fail(e, "top-k");
     return NBT_IG_OK;
 }

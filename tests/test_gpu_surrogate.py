@@ -131,8 +131,8 @@ def test_select_is_exact_reranking(nbt, ctx, setup):
 
 
 def test_bf16_kernels_against_unrounded_forward(nbt, ctx, setup):
-    """The BF16 kernels against a float64 forward that rounds nothing to BF16 (so the judge is
-    not the rounding-mirroring reference alone): max |err| <= 2e-2 * max |reference|."""
+    """The BF16 kernels against a float64 forward that rounds nothing to BF16 (so they are not
+    checked against the rounding-mirroring reference alone): max |err| <= 2e-2 * max |reference|."""
     import torch
     sc, poi, blob, sur, m = setup
     _note("surrogate vs unrounded float64 forward")

@@ -169,3 +169,14 @@ def test_batch_maps_sizes_and_seeds():
     again = batch_maps(n_maps=6, sizes=(16, 24), voxel=0.05, cfg=9, base_spheres=20)
     assert all(np.array_equal(a.P, b.P) for a, b in zip(maps, again))
     assert not np.array_equal(maps[0].P, maps[1].P) or maps[0].P.shape != maps[1].P.shape
+
+
+def test_surrogate_training_maps_roundtrip():
+    """The table-top surrogate's trainer ships maps as one code per voxel: the codes give back
+    the generator's probabilities exactly, and the PoIs are object tops of that map."""
+    from paper_2503_22588_amd import train_surrogate as T
+    codes, tops = T.tabletop_scene(22588 + 6000, n_pois=4)
+    sc = scene_tabletop(n=256, voxel=0.02, n_objects=200, seed=22588 + 6000)
+    assert codes.dtype == np.uint8 and np.array_equal(T.P_CODES[codes], sc.P)
+    assert tops.shape == (4, 3)
+    assert all(np.any(np.all(np.isclose(sc.extra["object_tops"], t, atol=1e-6), axis=1)) for t in tops)
