@@ -268,8 +268,13 @@ __global__ __launch_bounds__(256) void trunk_conv3_kernel(TrunkArgs p) {
 #pragma unroll
         for (int tap = 0; tap < 27; ++tap) b3[tap] = *reinterpret_cast<const bf16x8_t*>(wr + tap * 32);
     }
-    for (int i = t; i < 512 * 32 / 8; i += 256)
-        reinterpret_cast<bf16x8_t*>(s_act2)[i] = reinterpret_cast<const bf16x8_t*>(p.act2)[i];
+    {
+        bf16x8_t piece[8];                            // all requested before the first LDS write
+#pragma unroll
+        for (int j = 0; j < 8; ++j) piece[j] = reinterpret_cast<const bf16x8_t*>(p.act2)[t + 256 * j];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) reinterpret_cast<bf16x8_t*>(s_act2)[t + 256 * j] = piece[j];
+    }
     __syncthreads();
     const int mm = wave * 16 + row;
     const int z = mm >> 4, y = (mm >> 2) & 3, x = mm & 3;
@@ -309,8 +314,12 @@ __global__ __launch_bounds__(256) void trunk_conv4_kernel(TrunkArgs p) {
             b4[i] = ch < 54 ? *reinterpret_cast<const bf16x8_t*>(wr + ch * 32) : bf16_zero8();
         }
     }
-    for (int i = t; i < 64 * 64 / 8; i += 256)
-        reinterpret_cast<bf16x8_t*>(s_act3)[i] = reinterpret_cast<const bf16x8_t*>(p.act3)[i];
+    {
+        const bf16x8_t a0 = reinterpret_cast<const bf16x8_t*>(p.act3)[t];
+        const bf16x8_t a1 = reinterpret_cast<const bf16x8_t*>(p.act3)[t + 256];
+        reinterpret_cast<bf16x8_t*>(s_act3)[t] = a0;
+        reinterpret_cast<bf16x8_t*>(s_act3)[t + 256] = a1;
+    }
     __syncthreads();
     const int z = (row >> 2) & 1, y = (row >> 1) & 1, x = row & 1;      // rows 8..15 unused
     f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -418,10 +427,20 @@ __global__ __launch_bounds__(kMlpWaves * 64) void mlp_kernel(const float* __rest
 #pragma unroll
         for (int a = 0; a < 3; ++a) cen[i][a] = (wave_global < ngroup && p < n) ? poses[12 * (size_t)p + 9 + a] : 0.0f;
     }
-    for (int i = threadIdx.x; i < kHidden * kHidden / 8; i += blockDim.x) {
-        const int r = (i * 8) / kHidden, k = (i * 8) % kHidden;
-        *reinterpret_cast<bf16x8_t*>(sw2 + r * kW2Stride + k) =
-            *reinterpret_cast<const bf16x8_t*>(w2 + (size_t)r * kHidden + k);
+    {
+        // all 16 pieces of this thread requested before the first LDS write (a
+        // load-wait-store loop would pay one memory round trip per piece)
+        constexpr int kPer = kHidden * kHidden / 8 / (kMlpWaves * 64);
+        bf16x8_t piece[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j)
+            piece[j] = reinterpret_cast<const bf16x8_t*>(w2)[threadIdx.x + j * kMlpWaves * 64];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int i = threadIdx.x + j * kMlpWaves * 64;
+            const int r = (i * 8) / kHidden, k = (i * 8) % kHidden;
+            *reinterpret_cast<bf16x8_t*>(sw2 + r * kW2Stride + k) = piece[j];
+        }
     }
     for (int i = threadIdx.x; i < kHidden; i += blockDim.x) {
         *reinterpret_cast<float4*>(sw1d + w1d_slot(i)) = *reinterpret_cast<const float4*>(w1d + 4 * i);
@@ -467,7 +486,7 @@ __global__ __launch_bounds__(kMlpWaves * 64) void mlp_kernel(const float* __rest
         // `row` of each tile: the B operand of the h1 products below
         const float feat_in[2] = {kq == 0 ? u0[0] : kq == 1 ? u1[0] : kq == 2 ? u2[0] : dn[0],
                                   kq == 0 ? u0[1] : kq == 1 ? u1[1] : kq == 2 ? u2[1] : dn[1]};
-#pragma unroll 2
+#pragma unroll 1
         for (int ks = 0; ks < kHidden / 32; ++ks) {
             // h1 = c + W1d [u, dn] on the FP32 MFMA, transposed (neurons x poses):
             // block j of 16 neurons gives this lane neurons ks*32 + 16j + 4*kq + r
