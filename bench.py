@@ -264,12 +264,15 @@ def extra_trajectories(nbt, ctx, reps, ceilings=None):
     sc, cam, traj = w.maps[0], w.camera, w.poses[0]
     m = nbt.Map(ctx, sc.P, sc.voxel, sc.origin)
     dt = torch.from_numpy(traj).cuda()
-    layout, waves, _ = nbt.autotune_trajectories(m, cam, dt)
     out = {}
 
     def run():
         out["r"] = nbt.eval_trajectories(m, cam, dt, want_visits=False)
 
+    # the library's defaults first, so that the line states what the tuner buys
+    untuned = {"map_layout": nbt.LAYOUT_NAMES[m.info()["layout"]],
+               "ms_per_launch": _timed(run, reps, torch.cuda.current_stream())}
+    layout, waves, _ = nbt.autotune_trajectories(m, cam, dt)
     ms = _timed(run, reps, torch.cuda.current_stream())
     ig, counts, _ = out["r"]
     # visits from one untimed counting call, whose IG and counts must be the same bits
@@ -284,6 +287,7 @@ def extra_trajectories(nbt, ctx, reps, ceilings=None):
             "rays_per_s": rays / (ms * 1e-3), "voxel_steps_per_s": vis / (ms * 1e-3),
             "mean_unique_voxels": float(counts[:, 0].float().mean().item()),
             "map_layout": nbt.LAYOUT_NAMES[layout], "waves_per_group": waves,
+            "untuned": untuned, "tuner_speedup": untuned["ms_per_launch"] / ms,
             "note": "timed without the visit count (its voxel steps come from one untimed counting call); "
                     "includes the box pre-pass; nothing is read back to the host",
             "roofline": roofline_of("traj_union_kernel", vis / (ms * 1e-3), int(m.info()["device_bytes"]),
@@ -341,6 +345,10 @@ def extra_batch(nbt, ctx, reps, ceilings=None):
     ig = torch.empty(n, device="cuda")
     st = torch.empty(n, dtype=torch.int64, device="cuda")
     b = nbt.Batch(ctx, maps, w.camera, n)
+    # the library's defaults first, so that the line states what the tuner buys
+    untuned = {"launch": b.get_launch(), "map_layout": nbt.LAYOUT_NAMES[maps[0].info()["layout"]],
+               "batch_latency_ms": _timed(lambda: b.run(offsets, allp, ig, st), reps,
+                                          torch.cuda.current_stream())}
     layout, _ = b.autotune_layout(offsets, allp, ig, st)     # untimed set-up: map order, then shape
     best, _ = b.autotune(offsets, allp, ig, st)
     ms = _timed(lambda: b.run(offsets, allp, ig, st), reps, torch.cuda.current_stream())
@@ -350,6 +358,7 @@ def extra_batch(nbt, ctx, reps, ceilings=None):
            "batch_latency_ms": ms, "viewpoint_evals_per_s": n / (ms * 1e-3), "rays_per_s": rays / (ms * 1e-3),
            "voxel_steps_per_s": steps / (ms * 1e-3), "launch": b.get_launch(),
            "map_layout": nbt.LAYOUT_NAMES[layout],
+           "untuned": untuned, "tuner_speedup": untuned["batch_latency_ms"] / ms,
            "roofline": roofline_of("ig_batch_kernel", steps / (ms * 1e-3),
                                    sum(int(mm.info()["device_bytes"]) for mm in maps), ceilings)}
     b.close()
@@ -584,7 +593,12 @@ def main():
     steps = torch.empty(n, dtype=torch.int64, device="cuda")
     torch.cuda.synchronize()
     tuned = None
+    untuned = None
     if not args.layout and not args.launch:
+        # the library's defaults first, so that the line states what the tuner buys
+        untuned = {"map_layout": nbt.LAYOUT_NAMES[m.info()["layout"]], "launch": ctx.get_launch(),
+                   "kernel_ms": _timed(lambda: nbt.eval_viewpoints(m, cam, dposes, ig_out=ig, want_steps=False),
+                                       5, stream)}
         # untimed set-up: the library picks the map's storage order and the launch shape
         t_tune = time.perf_counter()
         launch, layout, tune_ms = nbt.autotune_map(m, cam, dposes, ig_out=ig)
@@ -663,6 +677,8 @@ def main():
         "voxel_steps_per_s": total_steps * args.steps / wall,
         "voxel_steps_per_step": total_steps,
         "kernel_ms": {"encode_map": enc_ms, "ig_viewpoints": ray_ms},
+        "untuned": untuned,
+        "tuner_speedup": untuned["kernel_ms"] / ray_ms if untuned else None,
         "roofline": {
             "kernel": "ig_viewpoints_kernel",
             "bound": "hbm",

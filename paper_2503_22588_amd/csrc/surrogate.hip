@@ -375,20 +375,32 @@ __global__ __launch_bounds__(256) void trunk_fc1_kernel(TrunkArgs p) {
 }
 
 // ---------------------------------------------------------------- MLP ------
-// Per pose: h1 = ReLU(c + W1d [u, dn]) (FP32 MFMA, stored BF16), h2 = ReLU(W2 h1 +
-// b2) on MFMA with W2 staged in LDS (rows padded to 264 halves so the 16
-// lanes reading one k-slice of 16 rows hit distinct banks), y = out_scale *
-// (W3 . h2 + b3).  One workgroup of 8 waves per CU shares the LDS copy of W2
-// (and of c, W1d, b2, W3); each wave takes 32 poses at a time, two 16-row A
-// tiles that share every W2 fragment read from LDS.
+// Per pose: h1 = ReLU(c + W1d [u, dn]) (FP32, stored BF16), h2 = ReLU(W2 h1 +
+// b2) (BF16 products, FP32 sums), y = out_scale * (W3 . h2 + b3).  One
+// workgroup of 8 waves per CU holds W2 (rows padded to 264 halves), W1d, c, b2
+// and W3 in LDS; each wave takes 32 poses at a time and computes h2 transposed
+// (outputs x poses) on v_mfma_f32_32x32x16_bf16, which from one wave issues at
+// about twice the rate of the 16x16x32 form per unit of work:
+//   * A = a W2 fragment: lane l holds output row l%32 of the tile and 8
+//     consecutive stored k positions (l/32)*8 .. +7 (one 16-byte LDS read);
+//   * B = h1 transposed: lane l holds pose l%32 and the same 8 k positions;
+//   * the 32 x 32 result gives lane l pose l%32 and outputs 8j + 4(l/32) + r
+//     (j, r = 0..3) at element 4j + r.
+// h1 comes from two chained v_mfma_f32_32x32x2_f32 per 32 neurons (neurons x
+// poses, K = the four inputs u0 u1 u2 dn, c as the accumulator input): its
+// result gives lane l pose l%32 and neurons 8j + 4(l/32) + r, which are the B
+// elements of two k-steps once W2's stored k order swaps bits 2 and 3 of the
+// index within each 16 (position q of a k-step holds neuron
+// 8((q>>2)&1) + 4(q>>3) + (q&3)).  fc3 sums each lane's outputs and one
+// exchange between the lane halves completes it.
 constexpr int kW2Stride = kHidden + 8;
 constexpr int kMlpWaves = 8;
-// W1d rows in LDS: 4 floats per neuron plus 4 of padding after every 16, so
-// that the four neurons k, k+8, k+16, k+24 one instruction reads (one per
-// 16-lane group) fall in different banks
-constexpr int kW1dWords = 4 * kHidden + 4 * (kHidden / 16);
-__device__ __forceinline__ int w1d_slot(int k) { return 4 * k + 4 * (k >> 4); }
-constexpr size_t kMlpLds = (size_t)kHidden * kW2Stride * sizeof(__bf16) + (size_t)(kW1dWords + 3 * kHidden) * sizeof(float);
+// W1d transposed in LDS (input-major), rows padded so that the two lane
+// halves reading inputs f and f+1 of 32 neurons hit different banks
+constexpr int kW1dStride = kHidden + 32;
+constexpr size_t kMlpLds =
+    (size_t)kHidden * kW2Stride * sizeof(__bf16) + (size_t)(4 * kW1dStride + 3 * kHidden) * sizeof(float);
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
 // Rank key of a value: larger values give larger keys, -0 and +0 the same
 // key, NaN the smallest.
@@ -410,22 +422,21 @@ __global__ __launch_bounds__(kMlpWaves * 64) void mlp_kernel(const float* __rest
     extern __shared__ __align__(16) unsigned char smem[];
     __bf16* sw2 = reinterpret_cast<__bf16*>(smem);
     float* sw1d = reinterpret_cast<float*>(smem + (size_t)kHidden * kW2Stride * sizeof(__bf16));
-    float* sc = sw1d + kW1dWords;
+    float* sc = sw1d + 4 * kW1dStride;
     float* sb2 = sc + kHidden;
     float* sw3 = sb2 + kHidden;
     const int lane = threadIdx.x & 63;
-    const int row = lane & 15, kq = lane >> 4;
+    const int col = lane & 31, half = lane >> 5;
     const uint32_t ngroup = (n + 31) / 32;
     const uint32_t wave_global = blockIdx.x * kMlpWaves + (threadIdx.x >> 6);
     const uint32_t waves = gridDim.x * kMlpWaves;
-    // this wave's first camera centres, requested before the LDS fill so that
-    // their latency passes during it
-    float cen[2][3];
+    // this lane's first camera centre (pose col of the wave's first group),
+    // requested before the LDS fill so that its latency passes during it
+    float cen[3];
+    {
+        const uint32_t p = wave_global * 32 + col;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const uint32_t p = wave_global * 32 + i * 16 + row;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) cen[i][a] = (wave_global < ngroup && p < n) ? poses[12 * (size_t)p + 9 + a] : 0.0f;
+        for (int a = 0; a < 3; ++a) cen[a] = (wave_global < ngroup && p < n) ? poses[12 * (size_t)p + 9 + a] : 0.0f;
     }
     {
         // all 16 pieces of this thread requested before the first LDS write (a
@@ -443,7 +454,9 @@ __global__ __launch_bounds__(kMlpWaves * 64) void mlp_kernel(const float* __rest
         }
     }
     for (int i = threadIdx.x; i < kHidden; i += blockDim.x) {
-        *reinterpret_cast<float4*>(sw1d + w1d_slot(i)) = *reinterpret_cast<const float4*>(w1d + 4 * i);
+        const f32x4_t w = *reinterpret_cast<const f32x4_t*>(w1d + 4 * i);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) sw1d[f * kW1dStride + i] = w[f];
         sc[i] = c[i];
         sb2[i] = b2[i];
         sw3[i] = w3[i];
@@ -451,94 +464,83 @@ __global__ __launch_bounds__(kMlpWaves * 64) void mlp_kernel(const float* __rest
     __syncthreads();
 
     for (uint32_t g = wave_global; g < ngroup; g += waves) {
-        float u0[2], u1[2], u2[2], dn[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const uint32_t p = g * 32 + i * 16 + row;
-            u0[i] = u1[i] = u2[i] = dn[i] = 0.0f;
-            if (p < n) {
-                const float vx = cen[i][0] - px;
-                const float vy = cen[i][1] - py;
-                const float vz = cen[i][2] - pz;
-                const float d = sqrtf(vx * vx + vy * vy + vz * vz);
-                const float inv = d > 0.0f ? 1.0f / d : 0.0f;
-                u0[i] = vx * inv;
-                u1[i] = vy * inv;
-                u2[i] = vz * inv;
-                dn[i] = (d - dist_mean) / dist_scale;
-            }
+        const uint32_t pose = g * 32 + col;
+        float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f, dn = 0.0f;
+        if (pose < n) {
+            const float vx = cen[0] - px;
+            const float vy = cen[1] - py;
+            const float vz = cen[2] - pz;
+            const float d = sqrtf(vx * vx + vy * vy + vz * vz);
+            const float inv = d > 0.0f ? 1.0f / d : 0.0f;
+            u0 = vx * inv;
+            u1 = vy * inv;
+            u2 = vz * inv;
+            dn = (d - dist_mean) / dist_scale;
         }
         {
-            const uint32_t g2 = g + waves;            // the next group's centres, if any
+            const uint32_t g2 = g + waves;            // the next group's centre, if any
+            const uint32_t p = g2 * 32 + col;
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const uint32_t p = g2 * 32 + i * 16 + row;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) cen[i][a] = (g2 < ngroup && p < n) ? poses[12 * (size_t)p + 9 + a] : 0.0f;
-            }
+            for (int a = 0; a < 3; ++a) cen[a] = (g2 < ngroup && p < n) ? poses[12 * (size_t)p + 9 + a] : 0.0f;
         }
-        // output-stationary: the 16 column tiles of h2 stay in registers while
-        // h1 is produced one 32-wide k-slice at a time
-        f32x4_t acc[2][kHidden / 16];
+        // B operands of the two h1 products: inputs (u0, u1), then (u2, dn),
+        // input `half` of each pair in this lane
+        const float fin0 = half ? u1 : u0, fin1 = half ? dn : u2;
+        f32x16_t acc[kHidden / 32];
 #pragma unroll
-        for (int nt = 0; nt < kHidden / 16; ++nt) acc[0][nt] = acc[1][nt] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
-        // this lane's input feature (u0, u1, u2 or dn by lane group) of pose
-        // `row` of each tile: the B operand of the h1 products below
-        const float feat_in[2] = {kq == 0 ? u0[0] : kq == 1 ? u1[0] : kq == 2 ? u2[0] : dn[0],
-                                  kq == 0 ? u0[1] : kq == 1 ? u1[1] : kq == 2 ? u2[1] : dn[1]};
+        for (int t = 0; t < kHidden / 32; ++t)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[t][e] = 0.0f;
 #pragma unroll 1
-        for (int ks = 0; ks < kHidden / 32; ++ks) {
-            // h1 = c + W1d [u, dn] on the FP32 MFMA, transposed (neurons x poses):
-            // block j of 16 neurons gives this lane neurons ks*32 + 16j + 4*kq + r
-            // (r = 0..3) of pose `row`, which become elements 4j + r of its A
-            // fragment (W2's columns are stored in the same order)
-            bf16x8_t a[2];
+        for (int blk = 0; blk < kHidden / 32; ++blk) {
+            // h1 of neurons 32 blk .. +31 for the wave's 32 poses
+            f32x16_t h;
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int nb = ks * 32 + 16 * j;
-                const float wa = sw1d[w1d_slot(nb + row) + kq];
-                const f32x4_t cc = {sc[nb + 4 * kq], sc[nb + 4 * kq + 1], sc[nb + 4 * kq + 2], sc[nb + 4 * kq + 3]};
+            for (int j = 0; j < 4; ++j) {
+                const f32x4_t cv = *reinterpret_cast<const f32x4_t*>(sc + 32 * blk + 8 * j + 4 * half);
 #pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    const f32x4_t h = __builtin_amdgcn_mfma_f32_16x16x4f32(wa, feat_in[i], cc, 0, 0, 0);
+                for (int r = 0; r < 4; ++r) h[4 * j + r] = cv[r];
+            }
+            const float wa0 = sw1d[half * kW1dStride + 32 * blk + col];
+            const float wa1 = sw1d[(2 + half) * kW1dStride + 32 * blk + col];
+            h = __builtin_amdgcn_mfma_f32_32x32x2f32(wa0, fin0, h, 0, 0, 0);
+            h = __builtin_amdgcn_mfma_f32_32x32x2f32(wa1, fin1, h, 0, 0, 0);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) a[i][4 * j + r] = (__bf16)(h[r] > 0.0f ? h[r] : 0.0f);
+            for (int t = 0; t < 2; ++t) {
+                // k-step 2 blk + t: elements 8t .. 8t+7 of h, ReLU, BF16
+                bf16x8_t hb;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float v = h[8 * t + e];
+                    hb[e] = (__bf16)(v > 0.0f ? v : 0.0f);
                 }
-            }
-            const __bf16* bk = sw2 + row * kW2Stride + ks * 32 + kq * 8;
+                const __bf16* ak = sw2 + col * kW2Stride + (2 * blk + t) * 16 + half * 8;
 #pragma unroll
-            for (int nt = 0; nt < kHidden / 16; ++nt) {
-                const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(bk + nt * 16 * kW2Stride);
-                acc[0][nt] = mfma16(a[0], b, acc[0][nt]);
-                acc[1][nt] = mfma16(a[1], b, acc[1][nt]);
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int nt = 0; nt < kHidden / 16; ++nt) {
-                const int col = nt * 16 + row;
-                const float bb = sb2[col], ww = sw3[col];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const float h2 = acc[i][nt][r] + bb;
-                    part[r] = __builtin_fmaf(ww, h2 > 0.0f ? h2 : 0.0f, part[r]);
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-#pragma unroll
-                for (int o = 1; o < 16; o <<= 1) part[r] += __shfl_xor(part[r], o, 64);
-            }
-            if (row == 0) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const uint32_t q = g * 32 + i * 16 + kq * 4 + r;
-                    if (q < n) pred[q] = out_scale * (part[r] + b3);
+                for (int ot = 0; ot < kHidden / 32; ++ot) {
+                    const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(ak + ot * 32 * kW2Stride);
+                    acc[ot] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, hb, acc[ot], 0, 0, 0);
                 }
             }
         }
+        // fc3: this lane's outputs 32 ot + 8j + 4 half + r of pose `col`
+        float part = 0.0f;
+#pragma unroll
+        for (int ot = 0; ot < kHidden / 32; ++ot) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int o = 32 * ot + 8 * j + 4 * half;
+                const f32x4_t bb = *reinterpret_cast<const f32x4_t*>(sb2 + o);
+                const f32x4_t ww = *reinterpret_cast<const f32x4_t*>(sw3 + o);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float h2 = acc[ot][4 * j + r] + bb[r];
+                    part = __builtin_fmaf(ww[r], h2 > 0.0f ? h2 : 0.0f, part);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);    // one tile's b2 / W3 reads at a time
+        }
+        part += __shfl_xor(part, 32, 64);
+        if (half == 0 && pose < n) pred[pose] = out_scale * (part + b3);
     }
 }
 

@@ -171,13 +171,11 @@ int nbt_ig_surrogate_create(nbt_ig_ctx* ctx, const void* weights, size_t nbytes,
         std::vector<float> b1(p.begin() + off, p.begin() + off + kHidden);
         off += kHidden;
         // W2 with its columns in the order the MLP kernel builds h1 in registers:
-        // within each 32-wide k slice, position 8g + e holds neuron 4g + e (e < 4)
-        // or 16 + 4g + e - 4 (e >= 4)
+        // stored position j holds neuron j with bits 2 and 3 of its index swapped
         std::vector<uint16_t> w2((size_t)kHidden * kHidden);
         for (int n = 0; n < kHidden; ++n)
             for (int j = 0; j < kHidden; ++j) {
-                const int ks = j / 32, g = (j % 32) / 8, e = j % 8;
-                const int src = ks * 32 + (e < 4 ? 4 * g + e : 16 + 4 * g + e - 4);
+                const int src = (j & ~0xC) | ((j & 4) << 1) | ((j & 8) >> 1);
                 w2[(size_t)n * kHidden + j] = to_bf16(p[off + (size_t)n * kHidden + src]);
             }
         off += w2.size();
