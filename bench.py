@@ -246,6 +246,25 @@ def level_fractions(steps_per_s, map_bytes, ceilings):
             "frac_vs_gather": steps_per_s / c["gather_words_per_s"]}
 
 
+BF16_PEAK_TFLOPS = 2500.0           # MI355X dense BF16 MFMA, datasheet
+MLP_FLOP_PER_POSE = 2 * (256 * 256 + 256 * 4 + 256)   # fc2 + the per-pose part of fc1 + fc3
+
+
+def measure_mfma_ceiling(nbt, ctx, reps=5, iters=2048):
+    """TFLOP/s of the library's MFMA probe (nbt_ig_probe_mfma): independent BF16 chains in
+    registers, both instruction forms, 1 and 2 waves per SIMD (the MLP runs 2)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, kind in (("16x16x32", nbt.binding.PROBE_MFMA_16X16X32_BF16),
+                       ("32x32x16", nbt.binding.PROBE_MFMA_32X32X16_BF16)):
+        for w in (1, 2):
+            sink, flops = nbt.binding.probe_mfma(ctx, kind, w, iters)
+            ms = _timed(lambda: nbt.binding.probe_mfma(ctx, kind, w, iters, sink), reps, stream)
+            out[f"{name}_bf16_{w}wave_tflops"] = flops / (ms * 1e-3) / 1e12
+    return out
+
+
 def roofline_of(kernel, steps_per_s, map_bytes, ceilings):
     """The contract's roofline object for a walk kernel: algorithmic bytes (4 per voxel step)
     against the HBM peak, plus the fractions of the measured ceilings of the map's level."""
@@ -397,7 +416,7 @@ def extra_surrogate(nbt, ctx, family="cfg1", n_maps=16, n_cand=65536, k_rescores
     blob = open(path, "rb").read()
     sur = nbt.Surrogate(ctx, blob)
     stream = torch.cuda.current_stream()
-    t_plain, nmae = [], []
+    t_plain, nmae, t_mlp = [], [], []
     per = {kr: {"agree": [], "ratio": [], "ms": []} for kr in k_rescores}
     for i in range(n_maps):
         P, vox, origin, poi, shell, CAM, seed = _held_out_map(family, i)
@@ -421,6 +440,10 @@ def extra_surrogate(nbt, ctx, family="cfg1", n_maps=16, n_cand=65536, k_rescores
             per[kr]["agree"].append(len(top & set(out["r"][0].cpu().numpy().tolist())) / k)
             per[kr]["ratio"].append(float(out["r"][1].cpu().numpy()[0]) / float(ex.max()))
         pred = sur.predict(m, poi, dp)
+        # the MLP alone: prediction (trunk + MLP) minus the trunk (features with no outputs)
+        if i < 4:
+            t_mlp.append(_timed(lambda: sur.predict(m, poi, dp, pred=pred), 20, stream)
+                         - _timed(lambda: sur.features(m, poi, want_patch=False, want_features=False), 20, stream))
         torch.cuda.synchronize()
         nmae.append(float(np.mean(np.abs(pred.cpu().numpy() - ex)) / np.mean(ex)))
         m.close()
@@ -445,7 +468,21 @@ def extra_surrogate(nbt, ctx, family="cfg1", n_maps=16, n_cand=65536, k_rescores
             "surrogate_evals_per_s": head["surrogate_evals_per_s"], "speedup": head["speedup"],
             "top10_agreement": head["top10_agreement"], "best_ig_ratio": head["best_ig_ratio"],
             "agreement_target": target, "operating_points": points,
-            "prediction_nmae": float(np.mean(nmae))}
+            "prediction_nmae": float(np.mean(nmae)),
+            "roofline": mlp_roofline(nbt, ctx, n_cand, float(np.mean(t_mlp)))}
+
+
+def mlp_roofline(nbt, ctx, n_cand, mlp_ms):
+    """The MLP's algorithmic FLOPs over its time, against the BF16 datasheet peak and against the
+    MFMA probe's rate for the MLP's instruction form and occupancy (32x32x16, 2 waves per SIMD)."""
+    ceil = measure_mfma_ceiling(nbt, ctx)
+    ach = n_cand * MLP_FLOP_PER_POSE / (mlp_ms * 1e-3) / 1e12
+    meas = ceil["32x32x16_bf16_2wave_tflops"]
+    return {"kernel": "mlp_kernel", "bound": "mfma", "achieved": ach, "peak": BF16_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": ach / BF16_PEAK_TFLOPS, "traffic": None,
+            "flop_per_launch": n_cand * MLP_FLOP_PER_POSE, "ms_per_launch": mlp_ms,
+            "frac_vs_measured_mfma": ach / meas, "measured_mfma_tflops": ceil,
+            "note": "MLP time = prediction (trunk + MLP) minus the trunk alone, HIP events, first 4 maps"}
 
 
 def e1_sweep(nbt, ctx, s_gs=(5, 50, 100, 200), n_ps=(100, 250, 500, 750, 1000), oracle_max_s=60.0,

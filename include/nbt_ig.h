@@ -523,6 +523,20 @@ int nbt_ig_probe_sink_words(const nbt_ig_ctx* ctx);
 int nbt_ig_probe_memory(nbt_ig_ctx* ctx, int kind, const void* buf, size_t bytes, uint32_t count,
                         uint32_t* sink, void* stream);
 
+/* ---- MFMA probe (measurement of the surrogate MLP's ceiling) ----------------------
+ * Launches cu_count * waves_per_simd workgroups of 4 waves (one per SIMD), each
+ * wave running `iters` rounds of independent BF16 MFMA accumulation chains on
+ * register operands (16 chains of v_mfma_f32_16x16x32_bf16, or 8 of
+ * v_mfma_f32_32x32x16_bf16), with no memory traffic in the loop.  sink (DEVICE,
+ * at least nbt_ig_probe_sink_words(ctx) words) receives one xor of the
+ * accumulators per workgroup; *flops (HOST, may be NULL) the launch's floating
+ * point operations (2 M N K per instruction), to be divided by the caller's own
+ * timing of the launch on `stream`.  waves_per_simd in [1, 8], iters >= 1. */
+#define NBT_IG_PROBE_MFMA_16X16X32_BF16 0
+#define NBT_IG_PROBE_MFMA_32X32X16_BF16 1
+int nbt_ig_probe_mfma(nbt_ig_ctx* ctx, int kind, int waves_per_simd, uint32_t iters, uint32_t* sink,
+                      double* flops, void* stream);
+
 const char* nbt_ig_status_string(int status);
 const char* nbt_ig_last_error(void);             /* thread-local; never NULL */
 int nbt_ig_abi_version(void);

@@ -88,6 +88,7 @@ _sig("nbt_ig_map_info", C.c_int, _vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.
 _sig("nbt_ig_eval_viewpoints", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp, _vp)
 _sig("nbt_ig_probe_sink_words", C.c_int, _vp)
 _sig("nbt_ig_probe_memory", C.c_int, _vp, C.c_int, _vp, C.c_size_t, _u32, _vp, _vp)
+_sig("nbt_ig_probe_mfma", C.c_int, _vp, C.c_int, C.c_int, _u32, _vp, C.POINTER(C.c_double), _vp)
 _sig("nbt_ig_eval_viewpoints_noalloc", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _vp, _vp, _vp)
 _sig("nbt_ig_eval_trajectories", C.c_int, _vp, C.POINTER(CameraT), _vp, _u32, _u32, _vp, _vp, _vp, _vp)
 _sig("nbt_ig_ctx_set_lds_budget", C.c_int, _vp, C.c_size_t)
@@ -352,6 +353,21 @@ def probe_memory(ctx, kind, buf, count, sink=None, stream=None):
                                     buf.numel() * buf.element_size(), int(count), _dev_ptr(sink, torch.int32, "sink"),
                                     _stream(stream)))
     return sink
+
+
+PROBE_MFMA_16X16X32_BF16, PROBE_MFMA_32X32X16_BF16 = 0, 1
+
+
+def probe_mfma(ctx, kind, waves_per_simd, iters, sink=None, stream=None):
+    """nbt_ig_probe_mfma; returns (sink tensor, floating point operations of the launch)."""
+    torch = _torch()
+    if sink is None:
+        sink = torch.empty(int(_lib.nbt_ig_probe_sink_words(ctx.handle)), dtype=torch.int32,
+                           device=f"cuda:{ctx.device}")
+    flops = C.c_double()
+    _check(_lib.nbt_ig_probe_mfma(ctx.handle, int(kind), int(waves_per_simd), int(iters),
+                                  _dev_ptr(sink, torch.int32, "sink"), C.byref(flops), _stream(stream)))
+    return sink, flops.value
 
 
 NOALLOC_MAX_VIEWPOINTS = 65536
@@ -676,12 +692,15 @@ class Surrogate:
                                             _stream(stream)))
         return idx, ig
 
-    def features(self, m: Map, poi, stream=None):
+    def features(self, m: Map, poi, stream=None, want_patch=True, want_features=True):
+        """The patch and the trunk's features (None where not wanted: the call then runs the
+        trunk alone)."""
         torch = _torch()
-        patch = torch.empty((2, 32, 32, 32), dtype=torch.float32, device="cuda")
-        feat = torch.empty(512, dtype=torch.float32, device="cuda")
-        _check(_lib.nbt_ig_surrogate_features(self.handle, m.handle, _poi(poi), _dev_ptr(patch, None, "patch"),
-                                              _dev_ptr(feat, None, "feat"), _stream(stream)))
+        patch = torch.empty((2, 32, 32, 32), dtype=torch.float32, device="cuda") if want_patch else None
+        feat = torch.empty(512, dtype=torch.float32, device="cuda") if want_features else None
+        _check(_lib.nbt_ig_surrogate_features(
+            self.handle, m.handle, _poi(poi), _dev_ptr(patch, None, "patch") if want_patch else None,
+            _dev_ptr(feat, None, "feat") if want_features else None, _stream(stream)))
         return patch, feat
 
     def close(self):

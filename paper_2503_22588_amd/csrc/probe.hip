@@ -1,6 +1,7 @@
-// probe.hip -- memory-system probes for the measurement of the ray kernels:
-// what the cache levels and HBM deliver to the access patterns of a voxel
-// walk, over a working set of a given size.
+// probe.hip -- probes for the measurement of the kernels' ceilings: what the
+// cache levels and HBM deliver to the access patterns of a voxel walk, over a
+// working set of a given size, and the issue rate of the BF16 MFMA forms the
+// surrogate uses.
 //
 //   stream        every 16-byte piece of the buffer read once per pass, in
 //                 coalesced order (the plain read bandwidth of the level the
@@ -76,6 +77,64 @@ __global__ __launch_bounds__(kProbeThreads) void probe_gather_kernel(const uint3
     probe_sink(x, sink);
 }
 
+// ---- MFMA issue rate: independent BF16 accumulation chains in registers,
+// no memory traffic in the loop.  Each block is 4 waves (one per SIMD); the
+// launch gives every SIMD `waves_per_simd` of them.  Operands come from the
+// thread index so that nothing folds; the sink takes the xor of the final
+// accumulators' bits.
+typedef __bf16 probe_bf16x8 __attribute__((ext_vector_type(8)));
+typedef float probe_f32x4 __attribute__((ext_vector_type(4)));
+typedef float probe_f32x16 __attribute__((ext_vector_type(16)));
+constexpr int kProbeChains16 = 16, kProbeChains32 = 8;
+
+__device__ __forceinline__ void probe_operands(probe_bf16x8& a, probe_bf16x8& b) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        a[i] = (__bf16)(1.0f + 0.001f * (float)((threadIdx.x + i) & 15));
+        b[i] = (__bf16)(1.0f - 0.001f * (float)i);
+    }
+}
+
+__global__ __launch_bounds__(kProbeThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void probe_mfma16_kernel(
+    uint32_t iters, uint32_t* __restrict__ sink) {
+    probe_bf16x8 a, b;
+    probe_operands(a, b);
+    probe_f32x4 acc[kProbeChains16];
+#pragma unroll
+    for (int c = 0; c < kProbeChains16; ++c) acc[c] = probe_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (uint32_t it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int c = 0; c < kProbeChains16; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
+    }
+    uint32_t x = 0;
+#pragma unroll
+    for (int c = 0; c < kProbeChains16; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x ^= __float_as_uint(acc[c][r]);
+    probe_sink(x, sink);
+}
+
+__global__ __launch_bounds__(kProbeThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void probe_mfma32_kernel(
+    uint32_t iters, uint32_t* __restrict__ sink) {
+    probe_bf16x8 a, b;
+    probe_operands(a, b);
+    probe_f32x16 acc[kProbeChains32];
+#pragma unroll
+    for (int c = 0; c < kProbeChains32; ++c)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[c][r] = 0.0f;
+    for (uint32_t it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int c = 0; c < kProbeChains32; ++c) acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[c], 0, 0, 0);
+    }
+    uint32_t x = 0;
+#pragma unroll
+    for (int c = 0; c < kProbeChains32; ++c)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x ^= __float_as_uint(acc[c][r]);
+    probe_sink(x, sink);
+}
+
 }  // namespace nbt
 
 using namespace nbt;
@@ -115,6 +174,32 @@ int nbt_ig_probe_memory(nbt_ig_ctx* ctx, int kind, const void* buf, size_t bytes
                            (uint32_t)(bytes / 4), count, sink);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "probe kernel");
+    return NBT_IG_OK;
+}
+
+int nbt_ig_probe_mfma(nbt_ig_ctx* ctx, int kind, int waves_per_simd, uint32_t iters, uint32_t* sink,
+                      double* flops, void* stream) {
+    if (!ctx || !sink) return fail(NBT_IG_EINVAL, "ctx or sink is NULL");
+    if (kind != NBT_IG_PROBE_MFMA_16X16X32_BF16 && kind != NBT_IG_PROBE_MFMA_32X32X16_BF16)
+        return fail(NBT_IG_EINVAL, "unknown MFMA probe %d", kind);
+    if (waves_per_simd < 1 || waves_per_simd > 8) return fail(NBT_IG_EINVAL, "waves_per_simd must lie in [1, 8]");
+    if (iters < 1) return fail(NBT_IG_EINVAL, "iters must be >= 1");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(NBT_IG_EDEVICE, "cannot select device %d", ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t blocks = (uint32_t)ctx->cu_count * (uint32_t)waves_per_simd;   // <= the sink's 8 per CU
+    const bool big = kind == NBT_IG_PROBE_MFMA_32X32X16_BF16;
+    if (big)
+        hipLaunchKernelGGL(probe_mfma32_kernel, dim3(blocks), dim3(kProbeThreads), 0, s, iters, sink);
+    else
+        hipLaunchKernelGGL(probe_mfma16_kernel, dim3(blocks), dim3(kProbeThreads), 0, s, iters, sink);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "MFMA probe kernel");
+    if (flops) {
+        // 2 x M x N x K per instruction: 16,384 (16x16x32) or 32,768 (32x32x16)
+        const double per = big ? 2.0 * 32 * 32 * 16 : 2.0 * 16 * 16 * 32;
+        *flops = (double)blocks * (kProbeThreads / 64) * (double)iters * (big ? kProbeChains32 : kProbeChains16) * per;
+    }
     return NBT_IG_OK;
 }
 

@@ -87,3 +87,12 @@ def test_noalloc_limit_matches_the_header():
     import paper_2503_22588_amd as nbt
     m = re.search(r"#define\s+NBT_IG_NOALLOC_MAX_VIEWPOINTS\s+(\d+)u?", open(HEADER).read())
     assert m and int(m.group(1)) == nbt.binding.NOALLOC_MAX_VIEWPOINTS
+
+
+def test_probe_constants_match_the_header():
+    import paper_2503_22588_amd as nbt
+    text = open(HEADER).read()
+    for name in ("PROBE_STREAM", "PROBE_GATHER", "PROBE_QUAD_GATHER", "PROBE_MFMA_16X16X32_BF16",
+                 "PROBE_MFMA_32X32X16_BF16"):
+        m = re.search(rf"#define\s+NBT_IG_{name}\s+(\d+)", text)
+        assert m and int(m.group(1)) == getattr(nbt.binding, name), name
