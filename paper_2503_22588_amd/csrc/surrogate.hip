@@ -548,11 +548,12 @@ __global__ __launch_bounds__(kMlpWaves * 64) void mlp_kernel(const float* __rest
 // The k largest of n predictions (ties to the lower index) as a set, with
 // their poses for the exact rescoring, in stages of one 1024-thread
 // workgroup per slice of items.  A workgroup holds its items in registers
-// (R per thread) and finds the exact k-th rank key T by three histogram
-// digits of the key (bits 31..20, 19..8, 7..0), each over the items still
-// tied with the bins chosen so far; of the keys equal to T it takes the
-// lowest indices, found by two histograms of index bits when more are equal
-// than needed.  Stage workgroups keep the k best of 4096 items each; the
+// (R per thread) and finds the exact k-th rank key by histogram digits of 12
+// bits of the key, from the highest bit in which its keys differ down, each
+// over the items still tied with the bins chosen so far, and stops when the
+// bin holding the k-th key is taken whole; of the keys equal to the k-th
+// key it takes the lowest indices, found by two histograms of index bits
+// when more are equal than needed.  Stage workgroups keep the k best of 4096 items each; the
 // last stage (one workgroup, at most 16,384 items) writes the chosen
 // candidates and copies their poses.  Sets are written in no particular
 // order: the final pick after rescoring orders by exact IG and index.
@@ -616,54 +617,99 @@ __device__ __forceinline__ uint32_t find_bin(uint32_t* s_hist, uint32_t bins, ui
     return d;
 }
 
-// Calls emit(key, idx) once for each of the k best valid items the workgroup
-// holds (all of them when there are at most k).
-template <int R, class EMIT>
-__device__ __forceinline__ void block_select(const uint32_t (&key)[R], const uint32_t (&idx)[R], uint32_t k,
-                                             uint32_t* s_hist, uint32_t* s_wave, uint32_t* s_out, EMIT emit) {
-    uint32_t beyond, in_bin, total;
-    // digit 1: bits 31..20
+// Max, min and count of the valid items' keys over the workgroup.
+template <int R>
+__device__ __forceinline__ void block_key_range(const uint32_t (&key)[R], const uint32_t (&idx)[R], uint32_t* s_red,
+                                                uint32_t& kmax, uint32_t& kmin, uint32_t& count) {
+    uint32_t mx = 0u, mn = 0xFFFFFFFFu, c = 0u;
 #pragma unroll
     for (int r = 0; r < R; ++r)
-        if (idx[r] != kNoItem) atomicAdd(&s_hist[key[r] >> 20], 1u);
+        if (idx[r] != kNoItem) {
+            mx = max(mx, key[r]);
+            mn = min(mn, key[r]);
+            ++c;
+        }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
+        mn = min(mn, (uint32_t)__shfl_xor(mn, o, 64));
+        c += __shfl_xor(c, o, 64);
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_red[3 * wave] = mx;
+        s_red[3 * wave + 1] = mn;
+        s_red[3 * wave + 2] = c;
+    }
     __syncthreads();
-    const uint32_t d1 = find_bin<true>(s_hist, 4096, k, s_wave, s_out, beyond, in_bin, total);
-    if (total <= k) {
+    kmax = 0u;
+    kmin = 0xFFFFFFFFu;
+    count = 0u;
+#pragma unroll
+    for (int w = 0; w < kSelThreads / 64; ++w) {
+        kmax = max(kmax, s_red[3 * w]);
+        kmin = min(kmin, s_red[3 * w + 1]);
+        count += s_red[3 * w + 2];
+    }
+    __syncthreads();
+}
+
+// Calls emit(key, idx) once for each of the k best valid items the workgroup
+// holds (all of them when there are at most k).  The key digits start below
+// the bits all valid keys share (found from their max and min), 12 bits at a
+// time, so that the first histogram is spread over the keys' actual range;
+// as soon as the bin holding the k-th key is taken whole, the items with a
+// digit prefix at or above it are the k best and no further pass is made.
+template <int R, class EMIT>
+__device__ __forceinline__ void block_select(const uint32_t (&key)[R], const uint32_t (&idx)[R], uint32_t k,
+                                             uint32_t* s_hist, uint32_t* s_wave, uint32_t* s_out,
+                                             uint32_t* s_red, EMIT emit) {
+    uint32_t kmax, kmin, count;
+    block_key_range<R>(key, idx, s_red, kmax, kmin, count);
+    if (count <= k) {
 #pragma unroll
         for (int r = 0; r < R; ++r)
             if (idx[r] != kNoItem) emit(key[r], idx[r]);
         return;
     }
-    uint32_t need = k - beyond;
-    // digit 2: bits 19..8 of the keys in bin d1
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-        if (idx[r] != kNoItem && (key[r] >> 20) == d1) atomicAdd(&s_hist[(key[r] >> 8) & 0xFFFu], 1u);
-    __syncthreads();
-    const uint32_t p2 = (d1 << 12) | find_bin<true>(s_hist, 4096, need, s_wave, s_out, beyond, in_bin, total);
-    need -= beyond;
-    // digit 3: bits 7..0
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-        if (idx[r] != kNoItem && (key[r] >> 8) == p2) atomicAdd(&s_hist[key[r] & 0xFFu], 1u);
-    __syncthreads();
-    const uint32_t T = (p2 << 8) | find_bin<true>(s_hist, 256, need, s_wave, s_out, beyond, in_bin, total);
-    need -= beyond;                                   // 1 <= need <= in_bin: keys equal to T to take
-    uint32_t imax = kNoItem;
-    if (in_bin > need) {
-        // the need lowest indices among the keys equal to T (index < 2^22)
+    uint32_t need = k;                                // items still to take from the current prefix
+    int hi = kmax == kmin ? -1 : 31 - __clz(kmax ^ kmin);   // highest bit in which valid keys differ
+    // the key bits above `hi` of the k-th key (none when the keys differ in bit 31)
+    uint32_t prefix = hi < 0 ? kmax : (hi == 31 ? 0u : kmax >> (hi + 1));
+    uint32_t beyond, in_bin, total;
+    while (hi >= 0) {
+        const int shift = hi >= 11 ? hi - 11 : 0;
+        const uint32_t bins = 1u << (hi - shift + 1);
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            if (idx[r] != kNoItem && key[r] == T) atomicAdd(&s_hist[idx[r] >> 11], 1u);
+            if (idx[r] != kNoItem && (key[r] >> hi >> 1) == prefix)
+                atomicAdd(&s_hist[(key[r] >> shift) & (bins - 1u)], 1u);
         __syncthreads();
-        const uint32_t hi = find_bin<false>(s_hist, 2048, need, s_wave, s_out, beyond, in_bin, total);
+        const uint32_t d = find_bin<true>(s_hist, bins, need, s_wave, s_out, beyond, in_bin, total);
         need -= beyond;
+        prefix = (prefix << (hi - shift + 1)) | d;
+        hi = shift - 1;
+        if (in_bin == need) {
+            // the whole bin is taken: the k best are the keys whose prefix is at least this one
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (idx[r] != kNoItem && key[r] == T && (idx[r] >> 11) == hi) atomicAdd(&s_hist[idx[r] & 0x7FFu], 1u);
-        __syncthreads();
-        imax = (hi << 11) | find_bin<false>(s_hist, 2048, need, s_wave, s_out, beyond, in_bin, total);
+            for (int r = 0; r < R; ++r)
+                if (idx[r] != kNoItem && (key[r] >> shift) >= prefix) emit(key[r], idx[r]);
+            return;
+        }
     }
+    const uint32_t T = prefix;                        // the k-th key; 1 <= need < its count
+    // the need lowest indices among the keys equal to T (index < 2^22)
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (idx[r] != kNoItem && key[r] == T) atomicAdd(&s_hist[idx[r] >> 11], 1u);
+    __syncthreads();
+    const uint32_t ihi = find_bin<false>(s_hist, 2048, need, s_wave, s_out, beyond, in_bin, total);
+    need -= beyond;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (idx[r] != kNoItem && key[r] == T && (idx[r] >> 11) == ihi) atomicAdd(&s_hist[idx[r] & 0x7FFu], 1u);
+    __syncthreads();
+    const uint32_t imax = (ihi << 11) | find_bin<false>(s_hist, 2048, need, s_wave, s_out, beyond, in_bin, total);
 #pragma unroll
     for (int r = 0; r < R; ++r)
         if (idx[r] != kNoItem && (key[r] > T || (key[r] == T && idx[r] <= imax))) emit(key[r], idx[r]);
@@ -681,6 +727,7 @@ __global__ __launch_bounds__(kSelThreads) void select_stage_kernel(const float* 
                                                                    uint32_t* __restrict__ out_idx) {
     __shared__ uint32_t s_hist[4096];
     __shared__ uint32_t s_wave[kSelThreads / 64];
+    __shared__ uint32_t s_red[3 * (kSelThreads / 64)];
     __shared__ uint32_t s_out[3];
     __shared__ uint32_t s_count;
     const uint32_t t = threadIdx.x;
@@ -702,7 +749,7 @@ __global__ __launch_bounds__(kSelThreads) void select_stage_kernel(const float* 
     __syncthreads();
     uint32_t* ok = out_key + (size_t)blockIdx.x * k;
     uint32_t* oi = out_idx + (size_t)blockIdx.x * k;
-    block_select<4>(key, idx, k, s_hist, s_wave, s_out, [&](uint32_t kk, uint32_t ii) {
+    block_select<4>(key, idx, k, s_hist, s_wave, s_out, s_red, [&](uint32_t kk, uint32_t ii) {
         const uint32_t p = atomicAdd(&s_count, 1u);
         if (p < k) {
             ok[p] = kk;
@@ -728,6 +775,7 @@ __global__ __launch_bounds__(kSelThreads) void select_final_kernel(const float* 
                                                                    float* __restrict__ cand_poses) {
     __shared__ uint32_t s_hist[4096];
     __shared__ uint32_t s_wave[kSelThreads / 64];
+    __shared__ uint32_t s_red[3 * (kSelThreads / 64)];
     __shared__ uint32_t s_out[3];
     __shared__ uint32_t s_count;
     const uint32_t t = threadIdx.x;
@@ -746,14 +794,22 @@ __global__ __launch_bounds__(kSelThreads) void select_final_kernel(const float* 
         }
     }
     __syncthreads();
-    block_select<R>(key, idx, k, s_hist, s_wave, s_out, [&](uint32_t, uint32_t ii) {
+    // the chosen indices go to LDS (the histogram's space, free again once
+    // the selection is made) and then out, with their poses, by all threads
+    uint32_t* s_cand = s_hist;
+    block_select<R>(key, idx, k, s_hist, s_wave, s_out, s_red, [&](uint32_t, uint32_t ii) {
         const uint32_t p = atomicAdd(&s_count, 1u);
-        if (p < k) {
-            cand[p] = ii;
-            if (poses)
-                for (int e = 0; e < 12; ++e) cand_poses[12 * (size_t)p + e] = poses[12 * (size_t)ii + e];
-        }
+        if (p < k) s_cand[p] = ii;
     });
+    __syncthreads();
+    const uint32_t got = min(s_count, k);
+    for (uint32_t p = t; p < got; p += kSelThreads) cand[p] = s_cand[p];
+    if (poses) {
+        for (uint32_t j = t; j < 12u * got; j += kSelThreads) {
+            const uint32_t p = j / 12u, e = j - 12u * p;
+            cand_poses[j] = poses[12 * (size_t)s_cand[p] + e];
+        }
+    }
 }
 
 // ---------------------------------------------------------------- top-k ----
