@@ -86,3 +86,29 @@ def test_next_best_view_selection(nbt, ctx):
         ref = S.top_k(vv, k)
         assert list(idx.cpu().numpy()) == list(ref)
         assert np.array_equal(val.cpu().numpy(), v[ref])
+
+
+def test_top_k_value_ranges(nbt, ctx):
+    """top-k where the radix digits adapt to the keys' range: values of both signs (keys that
+    differ in their top bit), -0 and +0 (equal values, lower index first), values that differ
+    only in their lowest mantissa bits, and infinities, the largest finite values and
+    denormals side by side."""
+    import torch
+    rng = np.random.default_rng(5)
+    eps = np.finfo(np.float32).eps
+    big, tiny = np.finfo(np.float32).max, np.float32(1e-40)
+    zeros = np.where(rng.random(20000) < 0.5, np.float32(-0.0), np.float32(0.0))
+    zeros[rng.integers(0, 20000, 3)] = 0.25
+    cases = {
+        "normal": rng.standard_normal(50000).astype(np.float32),
+        "signed zeros": zeros,
+        "low bits": (1.0 + rng.integers(0, 8, 30000) * eps).astype(np.float32),
+        "extremes": rng.choice(np.array([np.inf, -np.inf, big, -big, tiny, -tiny, 0.0, 1.0], np.float32), 10000),
+    }
+    for name, v in cases.items():
+        for k in (1, 7, 256, 1024):
+            idx, val = nbt.top_k(ctx, _dev(v), k)
+            torch.cuda.synchronize()
+            ref = S.top_k(v, k)
+            assert list(idx.cpu().numpy()) == list(ref), (name, k)
+            assert np.array_equal(val.cpu().numpy().view(np.uint32), v[ref].view(np.uint32)), (name, k)
