@@ -384,6 +384,23 @@ def extra_batch(nbt, ctx, reps, ceilings=None):
     return res
 
 
+def extra_top_k(nbt, ctx, reps=20):
+    """Next-best-view selection (nbt_ig_top_k): the k best of n per-perspective IG values, best
+    first, ties to the lower index; n = 4096 (one call of the headline workload), 65,536 and
+    2^20 seeded values with ties."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(17)
+    stream = torch.cuda.current_stream()
+    rows = []
+    for n, ks in ((4096, (1, 10)), (65536, (10, 256)), (1 << 20, (10, 1024))):
+        v = torch.from_numpy(np.round(rng.gamma(2.0, 0.1, n), 3).astype(np.float32)).cuda()
+        for k in ks:
+            ms = _timed(lambda: nbt.top_k(ctx, v, k), reps, stream)
+            rows.append({"n": n, "k": k, "us_per_call": ms * 1e3, "values_per_s": n / (ms * 1e-3)})
+    return {"workload": "k best of n IG values (gamma-distributed, rounded to 1e-3: many ties)", "rows": rows}
+
+
 def _held_out_map(family, i):
     """(P, voxel, origin, poi, shell, camera, seed) of held-out map i of a surrogate family (seeds
     outside the training ranges of paper_2503_22588_amd/train_surrogate.py)."""
@@ -552,7 +569,7 @@ def main():
     ap.add_argument("--no-ceilings", action="store_true",
                     help="skip the memory-probe ceilings (stream, gather) and the fractions against them")
     ap.add_argument("--only", choices=("trajectories", "batched", "surrogate", "surrogate_tabletop", "insert",
-                                       "ceilings"), default=None,
+                                       "top_k", "ceilings"), default=None,
                     help="only run one of the extra workloads (one JSON object)")
     ap.add_argument("--e1-sweep", action="store_true",
                     help="only run the N_P x s_G runtime sweep at 1 cm voxels (one JSON object per line)")
@@ -605,6 +622,7 @@ def main():
                "surrogate": lambda: extra_surrogate(nbt, cx),
                "surrogate_tabletop": lambda: extra_surrogate(nbt, cx, family="cfg2", n_maps=4),
                "insert": lambda: extra_insert(nbt, cx, reps=5),
+               "top_k": lambda: extra_top_k(nbt, cx),
                "ceilings": lambda: measure_ceilings(nbt, cx)}[args.only]
         print(json.dumps({args.only: run()}), flush=True)
         return
@@ -758,6 +776,8 @@ def main():
         result["surrogate_tabletop"] = extra_surrogate(nbt, cx, family="cfg2", n_maps=4)
         _log("measuring the map update by depth insertion ...")
         result["insert"] = extra_insert(nbt, cx, reps=5)
+        _log("measuring next-best-view selection (top-k) ...")
+        result["top_k"] = extra_top_k(nbt, cx)
         _log("measuring the runtime sweep at 1 cm voxels (compact) ...")
         result["e1_sweep"] = {
             "workload": "320^3 table-top map at 1 cm, N_P start points in the 1 m ball around an object top "

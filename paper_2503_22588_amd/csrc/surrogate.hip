@@ -2,10 +2,10 @@
 // MFMA (FP32 accumulation), radix selection of the candidates to rescore (also
 // the generic top-k) and the final pick after exact rescoring.
 //
-// Matrix fragments follow v_mfma_f32_16x16x32_bf16 (gfx950): for lane l,
-// A (16 x 32) row l%16 holds k = (l/16)*8 .. +7, B (32 x 16) column l%16 holds
-// the same k, and the 16 x 16 result gives lane l column l%16, rows
-// (l/16)*4 .. +3.
+// The trunk's fragments follow v_mfma_f32_16x16x32_bf16 (gfx950): for lane
+// l, A (16 x 32) row l%16 holds k = (l/16)*8 .. +7, B (32 x 16) column l%16
+// holds the same k, and the 16 x 16 result gives lane l column l%16, rows
+// (l/16)*4 .. +3.  The MLP uses the 32 x 32 forms (see there).
 #include "internal.hpp"
 #include "ray.hpp"
 #include "surrogate.hpp"
