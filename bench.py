@@ -766,13 +766,13 @@ def main():
         result["memory_ceilings"] = ceilings
     if not args.no_extras:
         cx = nbt.Context(0)            # default settings, untouched by the main line's tuning
-        _log("measuring trajectory IG (config 4) ...")
+        _log("measuring trajectory IG (256^3 map, 4096 trajectories x 24 poses) ...")
         result["trajectories"] = extra_trajectories(nbt, cx, reps=3, ceilings=ceilings)
-        _log("measuring the batched launch (config 3) ...")
+        _log("measuring the batched launch (64 maps, uneven perspective counts) ...")
         result["batched"] = extra_batch(nbt, cx, reps=5, ceilings=ceilings)
-        _log("measuring the surrogate (config 5) ...")
+        _log("measuring the surrogate (64^3 sphere maps, 65,536 candidates) ...")
         result["surrogate"] = extra_surrogate(nbt, cx)
-        _log("measuring the surrogate on table-top maps (config 5, config-2 family) ...")
+        _log("measuring the surrogate on 256^3 table-top maps (65,536 candidates) ...")
         result["surrogate_tabletop"] = extra_surrogate(nbt, cx, family="cfg2", n_maps=4)
         _log("measuring the map update by depth insertion ...")
         result["insert"] = extra_insert(nbt, cx, reps=5)
