@@ -403,12 +403,13 @@ def extra_top_k(nbt, ctx, reps=20):
 
 def _held_out_map(family, i):
     """(P, voxel, origin, poi, shell, camera, seed) of held-out map i of a surrogate family (seeds
-    outside the training ranges of paper_2503_22588_amd/train_surrogate.py)."""
+    outside the training ranges of paper_2503_22588_amd/train_surrogate.py; for the sphere maps
+    also outside the two held-out sets that chose among training runs)."""
     import numpy as np
     from workloads import scene_spheres, scene_tabletop
     from workloads.configs import CAM1, CAM2
     if family == "cfg1":
-        seed = 22588 + 5000 + 100000 + i
+        seed = 22588 + 5000 + 400000 + i
         sc = scene_spheres(n=64, voxel=0.05, n_spheres=10 + seed % 31, seed=seed)
         return sc.P, sc.voxel, sc.origin, np.asarray(sc.poi, np.float32), (0.4, 1.3), CAM1, seed
     seed = 22588 + 6000 + 100000 + i
@@ -418,7 +419,7 @@ def _held_out_map(family, i):
     return sc.P, sc.voxel, sc.origin, poi, (0.5, 1.2), CAM2, seed
 
 
-def extra_surrogate(nbt, ctx, family="cfg1", n_maps=16, n_cand=65536, k_rescores=(64, 256, 1024), k=10,
+def extra_surrogate(nbt, ctx, family="cfg1", n_maps=32, n_cand=65536, k_rescores=(64, 256, 1024), k=10,
                     target=0.95):
     """Surrogate-pruned selection vs plain raycasting on held-out maps of one scene family
     (cfg1: 64^3 sphere maps, cfg2: 256^3 table-top maps), at several rescoring budgets; the
