@@ -403,8 +403,8 @@ def extra_top_k(nbt, ctx, reps=20):
 
 def _held_out_map(family, i):
     """(P, voxel, origin, poi, shell, camera, seed) of held-out map i of a surrogate family (seeds
-    outside the training ranges of paper_2503_22588_amd/train_surrogate.py; for the sphere maps
-    also outside the two held-out sets that chose among training runs)."""
+    outside the training ranges of paper_2503_22588_amd/train_surrogate.py and outside the
+    held-out sets that chose among training runs)."""
     import numpy as np
     from workloads import scene_spheres, scene_tabletop
     from workloads.configs import CAM1, CAM2
@@ -412,7 +412,7 @@ def _held_out_map(family, i):
         seed = 22588 + 5000 + 400000 + i
         sc = scene_spheres(n=64, voxel=0.05, n_spheres=10 + seed % 31, seed=seed)
         return sc.P, sc.voxel, sc.origin, np.asarray(sc.poi, np.float32), (0.4, 1.3), CAM1, seed
-    seed = 22588 + 6000 + 100000 + i
+    seed = 22588 + 6000 + 400000 + i
     sc = scene_tabletop(n=256, voxel=0.02, n_objects=200, seed=seed)
     tops = sc.extra["object_tops"]
     poi = np.asarray(tops[np.random.default_rng(seed + 77).choice(len(tops), size=4, replace=False)[0]], np.float32)
