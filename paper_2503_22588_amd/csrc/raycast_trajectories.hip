@@ -272,8 +272,10 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(8, 8
         __syncthreads();
 
         for (uint32_t tile = (uint32_t)wave; tile < total; tile += WAVES) {
-            const uint32_t l = tile / tiles_pose;
-            const uint32_t tt = tile - l * tiles_pose;
+            // poses fastest: a workgroup's waves walk the same pixel tile of
+            // consecutive poses together, whose rays meet mostly the same voxels
+            const uint32_t tt = tile / L;
+            const uint32_t l = tile - tt * L;
             const float* pp = poses + 12 * ((size_t)t * L + l);
             float pose[12];
 #pragma unroll
