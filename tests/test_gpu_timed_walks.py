@@ -308,3 +308,26 @@ def test_whole_map_union_passes(nbt, ctx):
         for o in outs[1:]:
             assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1]), shape
         m.close()
+
+
+def test_depths_give_the_same_bits(nbt, ctx):
+    """The IG-only walk sums gains in binary32 runs of 8 slots at fixed slot indices, so
+    pipeline depths 2, 4 and 8 give the same IG bits (same workgroup shape)."""
+    import torch
+    w = make_config(1)
+    scene, cam, poses = w.maps[0], w.camera, w.poses[0]
+    _note("timed walk: IG bits across pipeline depths")
+    m = nbt.Map(ctx, scene.P, scene.voxel, scene.origin)
+    dp = _dev(poses)
+    got = {}
+    try:
+        for depth in (2, 4, 8):
+            _launch(ctx, depth=depth)
+            ig, _ = nbt.eval_viewpoints(m, cam, dp, want_steps=False)
+            torch.cuda.synchronize()
+            got[depth] = ig.cpu().numpy().view(np.uint32)
+    finally:
+        _launch(ctx)
+    for depth in (2, 4):
+        assert np.array_equal(got[depth], got[8]), depth
+    m.close()
