@@ -494,6 +494,10 @@ def mlp_roofline(nbt, ctx, n_cand, mlp_ms):
     """The MLP's algorithmic FLOPs over its time, against the BF16 datasheet peak and against the
     MFMA probe's rate for the MLP's instruction form and occupancy (32x32x16, 2 waves per SIMD)."""
     ceil = measure_mfma_ceiling(nbt, ctx)
+    if not mlp_ms > 0.0:              # a difference of two timings: noise must not make a rate of it
+        return {"kernel": "mlp_kernel", "bound": "mfma", "achieved": None, "peak": BF16_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": None, "traffic": None, "measured_mfma_tflops": ceil,
+                "note": f"prediction minus trunk time was {mlp_ms} ms: not a usable MLP time"}
     ach = n_cand * MLP_FLOP_PER_POSE / (mlp_ms * 1e-3) / 1e12
     meas = ceil["32x32x16_bf16_2wave_tflops"]
     return {"kernel": "mlp_kernel", "bound": "mfma", "achieved": ach, "peak": BF16_PEAK_TFLOPS,
