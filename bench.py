@@ -64,9 +64,17 @@ def kernel_fingerprint():
     return h.hexdigest()[:16]
 
 
-def measured_counters():
+def launch_key(layout, launch):
+    """'<map order> w,t,p,x,d': the map order and launch shape a counters summary was taken for."""
+    return f"{layout} " + ",".join(str(launch[k]) for k in
+                                   ("waves_per_group", "tile_w_log2", "tiles_per_wave", "xcd_remap",
+                                    "pipeline_depth"))
+
+
+def measured_counters(shape=None):
     """`key: value` lines of the committed counters summary, or None when it was taken
-    for other sources than the ones built now."""
+    for other sources than the ones built now, or (with `shape`, a launch_key) for another
+    map order or launch shape than the one timed."""
     path = os.path.join(ROOT, COUNTERS_PROFILE)
     if not os.path.exists(path):
         return None
@@ -76,6 +84,8 @@ def measured_counters():
             k, v = line[2:].split(": ", 1)
             vals[k.strip()] = v.strip().strip("`")
     if vals.get("fingerprint") != kernel_fingerprint():
+        return None
+    if shape is not None and vals.get("launch") != shape:
         return None
     return vals
 
@@ -750,7 +760,8 @@ def main():
             "algorithmic_gb_per_launch": alg_bytes / 1e9,
         },
     }
-    counters = measured_counters()
+    shape = launch_key(nbt.LAYOUT_NAMES[m.info()["layout"]], ctx.get_launch())
+    counters = measured_counters(shape)
     if counters is not None:
         # HBM-side bytes of one launch from the committed rocprofv3 passes (FETCH_SIZE and
         # WRITE_SIZE scaled by a copy kernel of known size), as a rate over this run's launch
@@ -764,7 +775,11 @@ def main():
             "valu_instr_per_cu_cycle": float(counters["VALU per CU-cycle"]),
             "tcp_accesses_per_gather": float(counters["L1 accesses per gather"]),
             "source": COUNTERS_PROFILE,
+            "launch": shape,
         }
+    else:
+        result["roofline"]["traffic_note"] = (f"no committed counters for these sources and this map order and "
+                                              f"launch shape ({shape})")
     if ceilings:
         result["roofline"]["levels"] = level_fractions(total_steps / (ray_ms * 1e-3), int(m.info()["device_bytes"]),
                                                        ceilings)
