@@ -1,6 +1,7 @@
 """The arithmetic of bench.py's roofline objects (CPU only): the algorithmic rate against the
 HBM peak, the choice of the measured ceiling by the map's size, the MLP's FLOP count, and a
-non-positive MLP time giving no rate."""
+non-positive MLP time giving no rate, and the committed counters applying only to the launch
+shape they were taken with."""
 
 import os
 import sys
@@ -47,3 +48,17 @@ def test_mlp_flops_and_guard(monkeypatch):
     for bad in (0.0, -0.001, float("nan")):
         r = bench.mlp_roofline(None, None, 65536, bad)
         assert r["achieved"] is None and r["frac"] is None
+
+
+def test_counters_only_for_their_launch_shape():
+    """The committed counters are used only for the sources, map order and launch shape they
+    were taken with."""
+    key = bench.launch_key("column4", {"waves_per_group": 2, "tile_w_log2": 3, "tiles_per_wave": 4,
+                                       "xcd_remap": 0, "pipeline_depth": 8})
+    assert key == "column4 2,3,4,0,8"
+    vals = bench.measured_counters()
+    if vals is None:
+        pytest.skip("the committed counters were taken for other sources")
+    assert "launch" in vals
+    assert bench.measured_counters(vals["launch"]) == vals
+    assert bench.measured_counters("linear 1,0,1,0,1") is None
