@@ -72,22 +72,28 @@ def launch_key(layout, launch):
 
 
 def measured_counters(shape=None):
-    """`key: value` lines of the committed counters summary, or None when it was taken
-    for other sources than the ones built now, or (with `shape`, a launch_key) for another
-    map order or launch shape than the one timed."""
+    """`key: value` lines of the committed counters summary for one map order and launch
+    shape: the block that starts at `- launch: <shape>` (the first block when `shape` is
+    None), with the summary's fingerprint.  None when the summary was taken for other
+    sources than the ones built now, or holds no block for `shape`."""
     path = os.path.join(ROOT, COUNTERS_PROFILE)
     if not os.path.exists(path):
         return None
-    vals = {}
+    common, blocks, cur = {}, [], None
     for line in open(path):
         if line.startswith("- ") and ": " in line:
             k, v = line[2:].split(": ", 1)
-            vals[k.strip()] = v.strip().strip("`")
-    if vals.get("fingerprint") != kernel_fingerprint():
+            k, v = k.strip(), v.strip().strip("`")
+            if k == "launch":
+                cur = {}
+                blocks.append(cur)
+            (common if cur is None else cur)[k] = v
+    if common.get("fingerprint") != kernel_fingerprint() or not blocks:
         return None
-    if shape is not None and vals.get("launch") != shape:
-        return None
-    return vals
+    for b in blocks:
+        if shape is None or b["launch"] == shape:
+            return {**common, **b}
+    return None
 
 
 def cpu_identity():

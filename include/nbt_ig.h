@@ -376,8 +376,8 @@ int nbt_ig_batch_set_launch(nbt_ig_batch* batch, const nbt_ig_launch* launch);
 int nbt_ig_batch_get_launch(const nbt_ig_batch* batch, nbt_ig_launch* launch, uint32_t* persistent_groups);
 
 /* ---- autotuning ----------------------------------------------------------------------
- * Time candidate launch shapes (every combination of waves_per_group 2/4/8,
- * tile_w_log2 2/3/4, tiles_per_wave 0/4/16 and pipeline_depth 2/4/8: 81
+ * Time candidate launch shapes (every combination of waves_per_group 1/2/4/8,
+ * tile_w_log2 2/3/4, tiles_per_wave 0/2/4/16 and pipeline_depth 2/4/8: 144
  * shapes, each run once untimed and then timed) on the given inputs, keep
  * the fastest in the context (or batch) and report it with its
  * mean time per launch in milliseconds (HOST outputs).  Outputs are written

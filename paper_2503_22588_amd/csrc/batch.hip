@@ -121,17 +121,21 @@ int fastest_layout(const float* ms) {
     return best;
 }
 
-// Exhaustive search over the launch grid (3 x 3 x 3 x 3 = 81 shapes): every
+// Exhaustive search over the launch grid (4 x 3 x 4 x 3 = 144 shapes): every
 // shape is applied, run once untimed (warm-up, graph rebuild) and timed over
 // `reps` runs; the fastest is kept.  A search one parameter at a time was
-// seen to stop in a local optimum 10 % slower than the grid's best.
+// seen to stop in a local optimum 10 % slower than the grid's best.  Single
+// waves and 2 tiles per wave are in the grid because the cross-workgroup
+// combine costs a workgroup only its atomics: many small workgroups balance
+// best on the large table-top workload.
 template <class Apply, class Run>
 int launch_search(VpLaunch start, hipStream_t s, int reps, Apply&& apply, Run&& run, VpLaunch* best_out,
                   float* best_ms_out) {
-    static const int waves[] = {2, 4, 8};
+    static const int waves[] = {1, 2, 4, 8};
     static const int tiles[] = {2, 3, 4};
-    static const int tpws[] = {0, 4, 16};          // 0: balanced for the camera
+    static const int tpws[] = {0, 2, 4, 16};       // 0: balanced for the camera
     static const int depths[] = {2, 4, 8};
+    constexpr int kW = 4, kT = 3, kP = 4, kD = 3;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return fail(NBT_IG_EDEVICE, "hipEventCreate failed");
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -154,12 +158,12 @@ int launch_search(VpLaunch start, hipStream_t s, int reps, Apply&& apply, Run&& 
     VpLaunch best = start;
     float best_ms = 0.0f;
     int rc = NBT_IG_OK;
-    for (int a = 0; a < 81 && rc == NBT_IG_OK; ++a) {
+    for (int a = 0; a < kW * kT * kP * kD && rc == NBT_IG_OK; ++a) {
         VpLaunch L = start;
-        L.waves = waves[a % 3];
-        L.tile_w_log2 = tiles[(a / 3) % 3];
-        L.tiles_per_wave = tpws[(a / 9) % 3];
-        L.depth = depths[a / 27];
+        L.waves = waves[a % kW];
+        L.tile_w_log2 = tiles[(a / kW) % kT];
+        L.tiles_per_wave = tpws[(a / (kW * kT)) % kP];
+        L.depth = depths[a / (kW * kT * kP)];
         float ms = 0.0f;
         rc = time(L, &ms);
         if (rc == NBT_IG_OK && (a == 0 || ms < best_ms)) {

@@ -59,6 +59,27 @@ def test_counters_only_for_their_launch_shape():
     vals = bench.measured_counters()
     if vals is None:
         pytest.skip("the committed counters were taken for other sources")
-    assert "launch" in vals
+    assert "launch" in vals and "fingerprint" in vals
     assert bench.measured_counters(vals["launch"]) == vals
     assert bench.measured_counters("linear 1,0,1,0,1") is None
+
+
+def test_counters_blocks_per_launch_shape(tmp_path, monkeypatch):
+    """A summary may hold one block of values per launch shape; each shape gets its own."""
+    fp = bench.kernel_fingerprint()
+    (tmp_path / "c.md").write_text(f"text\n\n- fingerprint: `{fp}`\n\n- launch: column4 1,3,4,0,8\n"
+                                   "- traffic bytes per launch: 100\n- TA busy fraction: 0.9\n\n"
+                                   "- launch: column4 1,3,2,0,8\n- traffic bytes per launch: 200\n"
+                                   "- TA busy fraction: 0.8\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "COUNTERS_PROFILE", "c.md")
+    monkeypatch.setattr(bench, "kernel_fingerprint", lambda: fp)
+    a = bench.measured_counters("column4 1,3,4,0,8")
+    b = bench.measured_counters("column4 1,3,2,0,8")
+    assert a["traffic bytes per launch"] == "100" and a["TA busy fraction"] == "0.9"
+    assert b["traffic bytes per launch"] == "200" and b["TA busy fraction"] == "0.8"
+    assert a["fingerprint"] == fp == b["fingerprint"]
+    assert bench.measured_counters() == a
+    assert bench.measured_counters("column4 2,3,4,0,8") is None
+    monkeypatch.setattr(bench, "kernel_fingerprint", lambda: "other")
+    assert bench.measured_counters("column4 1,3,4,0,8") is None
