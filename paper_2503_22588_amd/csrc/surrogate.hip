@@ -20,48 +20,64 @@ __device__ __forceinline__ f32x4_t mfma16(const bf16x8_t& a, const bf16x8_t& b, 
 }
 
 // ---------------------------------------------------------------- patch ----
-// One thread per cell: occupied and unknown voxel counts over the cell's f^3
-// voxels (voxels outside the map count as neither), divided by f^3.
+// Occupied and unknown voxel counts over each cell's f^3 voxels (voxels
+// outside the map count as neither), divided by f^3.  One workgroup per run
+// of kPatchRun cells along x; its threads take the run's rows of f voxels
+// along x (cell fastest, then y, then z, so a wave reads contiguous runs of
+// the map) and add their counts in LDS.
+constexpr int kPatchRun = 8;
+
 __global__ __launch_bounds__(256) void patch_kernel(DevMap m, int f, int i0x, int i0y, int i0z,
                                                     __bf16* __restrict__ out_bf16,
                                                     float* __restrict__ out_f32) {
-    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= kPatchCells) return;
-    const int cx = cell % kGrid, cy = (cell / kGrid) % kGrid, cz = cell / (kGrid * kGrid);
+    __shared__ uint32_t s_occ[kPatchRun], s_unk[kPatchRun];
+    const int cell0 = (int)blockIdx.x * kPatchRun;
+    const int cx0 = cell0 % kGrid, cy = (cell0 / kGrid) % kGrid, cz = cell0 / (kGrid * kGrid);
+    if (threadIdx.x < kPatchRun) s_occ[threadIdx.x] = s_unk[threadIdx.x] = 0u;
+    __syncthreads();
     const __amdgpu_buffer_rsrc_t rs = map_rsrc(m);
-    uint32_t occ = 0, unk = 0;
-    for (int dz = 0; dz < f; ++dz) {
-        const int z = i0z + cz * f + dz;
-        if (z < 0 || z >= m.nz) continue;
-        for (int dy = 0; dy < f; ++dy) {
-            const int y = i0y + cy * f + dy;
-            if (y < 0 || y >= m.ny) continue;
-            for (int dx = 0; dx < f; ++dx) {
-                const int x = i0x + cx * f + dx;
-                if (x < 0 || x >= m.nx) continue;
-                const uint32_t w = load_word(rs, voxel_offset(m, x, y, z));
-                occ += (w & kOccBit) ? 1u : 0u;
-                unk += (w == kGainOne) ? 1u : 0u;
-            }
+    const int rows = kPatchRun * f * f;
+    for (int it = (int)threadIdx.x; it < rows; it += (int)blockDim.x) {
+        const int c = it % kPatchRun, r = it / kPatchRun;
+        const int y = i0y + cy * f + r % f, z = i0z + cz * f + r / f;
+        if (y < 0 || y >= m.ny || z < 0 || z >= m.nz) continue;
+        const int x0 = i0x + (cx0 + c) * f;
+        uint32_t occ = 0, unk = 0;
+#pragma unroll 4
+        for (int dx = 0; dx < f; ++dx) {
+            const int x = x0 + dx;
+            const uint32_t w = (x >= 0 && x < m.nx) ? load_word(rs, voxel_offset(m, x, y, z)) : 0u;
+            occ += (w & kOccBit) ? 1u : 0u;
+            unk += (w == kGainOne) ? 1u : 0u;
         }
+        if (occ) atomicAdd(&s_occ[c], occ);
+        if (unk) atomicAdd(&s_unk[c], unk);
     }
-    const float vol = (float)(f * f * f);
-    const float fo = (float)occ / vol, fu = (float)unk / vol;
-    if (out_bf16) {
-        out_bf16[cell] = (__bf16)fo;
-        out_bf16[kPatchCells + cell] = (__bf16)fu;
-    }
-    if (out_f32) {
-        out_f32[cell] = fo;
-        out_f32[kPatchCells + cell] = fu;
+    __syncthreads();
+    if (threadIdx.x < kPatchRun) {
+        const int cell = cell0 + (int)threadIdx.x;
+        const float vol = (float)((double)f * f * f);
+        const float fo = (float)s_occ[threadIdx.x] / vol, fu = (float)s_unk[threadIdx.x] / vol;
+        if (out_bf16) {
+            out_bf16[cell] = (__bf16)fo;
+            out_bf16[kPatchCells + cell] = (__bf16)fu;
+        }
+        if (out_f32) {
+            out_f32[cell] = fo;
+            out_f32[kPatchCells + cell] = fu;
+        }
     }
 }
 
 // ---------------------------------------------------------------- trunk ----
 // The trunk in four launches.  trunk_front: workgroup b of 64 owns a 2^3 block
-// of the 8^3 conv2 outputs.  It counts the 11^3 patch cells that block
-// depends on (cells outside the 32^3 patch are conv1's zero padding) straight
-// from the map, rounds the fractions to BF16 in LDS, computes the 5^3 conv1
+// of the 8^3 conv2 outputs.  It takes the 11^3 patch cells that block depends
+// on (cells outside the 32^3 patch are conv1's zero padding) into LDS as BF16
+// fractions: counted straight from the map, one thread per cell, when cells
+// are at most kFrontCountMaxF voxels wide, else read from the patch that
+// launch_patch counted over the whole chip first (64 workgroups counting
+// 5^3-voxel cells took 74 us; the separate pass spreads them over every CU).
+// It then computes the 5^3 conv1
 // outputs around its block (those outside the 16^3 grid are conv2's zero
 // padding) and its eight conv2 positions, all from LDS, and stores them
 // channel-last, [z][y][x][32].  conv3, conv4 and the pose-independent part
@@ -95,56 +111,54 @@ __device__ __forceinline__ void tap_dxyz(int tap, int& dz, int& dy, int& dx) {
     dx = tap % 3;
 }
 
-// Occupied and unknown voxel counts of the 11^3 patch cells 8b-3 .. 8b+7 (per
-// axis) that block b depends on, added into cnt.  One thread per row of a
-// cell (F voxels along x); F = 0 reads the cell size at run time.
+// The 11^3 patch cells 8b-3 .. 8b+7 (per axis) that block b depends on, as
+// BF16 fractions in `patch`: counted from the map, one thread per cell (F
+// voxels per cell and axis), or read from the counted patch p.patch.
 template <int F>
-__device__ __forceinline__ void count_region(const TrunkArgs& p, int bx, int by, int bz,
-                                             unsigned (&cnt)[2][kCells3]) {
-    const int f = F > 0 ? F : p.f;
+__device__ __forceinline__ void front_cells(const TrunkArgs& p, int bx, int by, int bz,
+                                            __bf16 (&patch)[2][kCells3]) {
     const int cx0 = 8 * bx - 3, cy0 = 8 * by - 3, cz0 = 8 * bz - 3;
     const DevMap& m = p.m;
-    const int R = kCells * f;
-    const uint32_t rows = (uint32_t)R * (uint32_t)R * kCells;          // (z voxel, y voxel, x cell)
     const __amdgpu_buffer_rsrc_t rs = map_rsrc(m);
-#pragma unroll 4
-    for (uint32_t r = threadIdx.x; r < rows; r += kTrunkThreads) {
-        const int clx = (int)(r % kCells);
-        const uint32_t q = r / kCells;
-        const int yv = (int)(q % (uint32_t)R), zv = (int)(q / (uint32_t)R);
-        const int cly = yv / f, clz = zv / f;
+    for (int cell = threadIdx.x; cell < kCells3; cell += kTrunkThreads) {
+        const int clx = cell % kCells, cly = (cell / kCells) % kCells, clz = cell / (kCells * kCells);
         const int cx = cx0 + clx, cy = cy0 + cly, cz = cz0 + clz;
-        const int y = p.i0y + cy * f + (yv - cly * f), z = p.i0z + cz * f + (zv - clz * f);
-        const bool in_patch = (unsigned)cx < (unsigned)kGrid && (unsigned)cy < (unsigned)kGrid &&
-                              (unsigned)cz < (unsigned)kGrid;
-        const bool in_map = y >= 0 && y < m.ny && z >= 0 && z < m.nz;
-        if (!(in_patch && in_map)) continue;
-        const int x0 = p.i0x + cx * f;
-        uint32_t occ = 0, unk = 0;
-        if constexpr (F > 0) {
+        __bf16 fo = (__bf16)0.0f, fu = (__bf16)0.0f;
+        if ((unsigned)cx < (unsigned)kGrid && (unsigned)cy < (unsigned)kGrid && (unsigned)cz < (unsigned)kGrid) {
+            if constexpr (F == 0) {
+                const int pc = (cz * kGrid + cy) * kGrid + cx;
+                fo = p.patch[pc];
+                fu = p.patch[kPatchCells + pc];
+            } else {
+                const int x0 = p.i0x + cx * F, y0 = p.i0y + cy * F, z0 = p.i0z + cz * F;
+                uint32_t occ = 0, unk = 0;
 #pragma unroll
-            for (int d = 0; d < F; ++d) {
-                const int x = x0 + d;
-                const uint32_t w = (x >= 0 && x < m.nx) ? load_word(rs, voxel_offset(m, x, y, z)) : 0u;
-                occ += (w & kOccBit) ? 1u : 0u;
-                unk += (w == kGainOne) ? 1u : 0u;
-            }
-        } else {
-            const int xa = x0 < 0 ? 0 : x0, xb = x0 + f > m.nx ? m.nx : x0 + f;
-            for (int x = xa; x < xb; ++x) {
-                const uint32_t w = load_word(rs, voxel_offset(m, x, y, z));
-                occ += (w & kOccBit) ? 1u : 0u;
-                unk += (w == kGainOne) ? 1u : 0u;
+                for (int dz = 0; dz < F; ++dz) {
+#pragma unroll
+                    for (int dy = 0; dy < F; ++dy) {
+                        const int y = y0 + dy, z = z0 + dz;
+                        const bool yz = y >= 0 && y < m.ny && z >= 0 && z < m.nz;
+#pragma unroll
+                        for (int dx = 0; dx < F; ++dx) {
+                            const int x = x0 + dx;
+                            const uint32_t w =
+                                (yz && x >= 0 && x < m.nx) ? load_word(rs, voxel_offset(m, x, y, z)) : 0u;
+                            occ += (w & kOccBit) ? 1u : 0u;
+                            unk += (w == kGainOne) ? 1u : 0u;
+                        }
+                    }
+                }
+                const float vol = (float)(F * F * F);
+                fo = (__bf16)((float)occ / vol);
+                fu = (__bf16)((float)unk / vol);
             }
         }
-        const int cell = (clz * kCells + cly) * kCells + clx;
-        if (occ) atomicAdd(&cnt[0][cell], occ);
-        if (unk) atomicAdd(&cnt[1][cell], unk);
+        patch[0][cell] = fo;
+        patch[1][cell] = fu;
     }
 }
 
 __global__ __launch_bounds__(kTrunkThreads) void trunk_front_kernel(TrunkArgs p) {
-    __shared__ unsigned s_cnt[2][kCells3];
     __shared__ __bf16 s_patch[2][kCells3];
     __shared__ __align__(16) __bf16 s_act1[kC1 * kC1 * kC1 * 16];
     __shared__ f32x4_t s_part[8][64];
@@ -153,27 +167,11 @@ __global__ __launch_bounds__(kTrunkThreads) void trunk_front_kernel(TrunkArgs p)
     const int wave = t >> 6, lane = t & 63, row = lane & 15, kq = lane >> 4;
     const int bx = blockIdx.x & 3, by = (blockIdx.x >> 2) & 3, bz = blockIdx.x >> 4;
 
-    // ---- patch cells 8b-3 .. 8b+7 per axis: occupied and unknown counts ----
-    for (int i = t; i < kCells3; i += kTrunkThreads) s_cnt[0][i] = s_cnt[1][i] = 0u;
-    __syncthreads();
-    switch (p.f) {                    // a constant cell size lets the row loop unroll
-    case 1: count_region<1>(p, bx, by, bz, s_cnt); break;
-    case 2: count_region<2>(p, bx, by, bz, s_cnt); break;
-    case 3: count_region<3>(p, bx, by, bz, s_cnt); break;
-    case 4: count_region<4>(p, bx, by, bz, s_cnt); break;
-    case 5: count_region<5>(p, bx, by, bz, s_cnt); break;
-    case 6: count_region<6>(p, bx, by, bz, s_cnt); break;
-    case 8: count_region<8>(p, bx, by, bz, s_cnt); break;
-    default: count_region<0>(p, bx, by, bz, s_cnt); break;
-    }
-    __syncthreads();
-    {
-        const float vol = (float)(p.f * p.f * p.f);
-        for (int i = t; i < kCells3; i += kTrunkThreads) {
-            s_patch[0][i] = (__bf16)((float)s_cnt[0][i] / vol);
-            s_patch[1][i] = (__bf16)((float)s_cnt[1][i] / vol);
-        }
-    }
+    // ---- patch cells 8b-3 .. 8b+7 per axis ----
+    static_assert(kFrontCountMaxF == 2, "the front counts cells of 1 or 2 voxels");
+    if (p.patch) front_cells<0>(p, bx, by, bz, s_patch);
+    else if (p.f == 1) front_cells<1>(p, bx, by, bz, s_patch);
+    else front_cells<2>(p, bx, by, bz, s_patch);
     __syncthreads();
 
     // ---- conv1 outputs 4b-1 .. 4b+3 per axis (125 positions x 16 channels) ----
@@ -858,8 +856,10 @@ __global__ __launch_bounds__(kMaxRescore) void final_select_kernel(const float* 
 
 hipError_t launch_patch(const DevMap& m, int f, const int i0[3], __bf16* out_bf16, float* out_f32,
                         hipStream_t s) {
-    hipLaunchKernelGGL(patch_kernel, dim3(kPatchCells / 256), dim3(256), 0, s, m, f, i0[0], i0[1], i0[2],
-                       out_bf16, out_f32);
+    const int64_t rows = (int64_t)kPatchRun * f * f;
+    const int threads = rows >= 256 ? 256 : (int)((rows + 63) / 64 * 64);
+    hipLaunchKernelGGL(patch_kernel, dim3(kPatchCells / kPatchRun), dim3(threads), 0, s, m, f, i0[0], i0[1],
+                       i0[2], out_bf16, out_f32);
     return hipGetLastError();
 }
 

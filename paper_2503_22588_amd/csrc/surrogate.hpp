@@ -14,6 +14,9 @@ constexpr uint32_t kMaxCandidates = 1u << 22;      // candidate index fits 22 bi
 constexpr int kConvIn[4] = {2, 16, 32, 64};
 constexpr int kConvOut[4] = {16, 32, 64, 64};
 constexpr int kTrunkBlocks = 64;                   // conv2's 8^3 outputs in 2^3 blocks
+// Cells at most this many voxels wide are counted by the trunk's first
+// launch itself; wider ones by launch_patch over the whole chip first.
+constexpr int kFrontCountMaxF = 2;
 
 // Padded reduction length of conv layer l in the library's weight order:
 // conv1 k = ci*27 + tap, the others k = tap*cin + ci (tap = (dz*3+dy)*3+dx).
@@ -24,6 +27,7 @@ struct TrunkArgs {
     DevMap m;
     int f;                       // map voxels per patch cell and axis
     int i0x, i0y, i0z;           // voxel of the patch's first cell corner
+    const __bf16* patch;         // the counted patch [2][32^3] (cells wider than kFrontCountMaxF), or null
     const __bf16* w[4];          // conv weights [cout][conv_kpad(l)]
     const float* b[4];           // conv biases [cout]
     const __bf16* w1f;           // fc1 weights on the features [256][512]

@@ -34,6 +34,7 @@ struct nbt_ig_surrogate {
     __bf16* act2 = nullptr;      // conv2 output, channel-last
     __bf16* act3 = nullptr;      // conv3 output, channel-last
     __bf16* feat = nullptr;      // trunk features
+    __bf16* patch = nullptr;     // the counted patch, for cells wider than the trunk counts itself
     float* c = nullptr;
     float* pred = nullptr;       // predictions of a selection (grown stream-ordered)
     size_t pred_bytes = 0;
@@ -76,7 +77,8 @@ int run_trunk(nbt_ig_surrogate* s, const nbt_ig_map* map, const float poi[3], fl
         i0[a] = (int)q - (kGrid / 2) * f;
     }
     hipError_t e = hipSuccess;
-    if (patch_f32) e = launch_patch(map->dm, f, i0, nullptr, patch_f32, st);
+    const bool counted = f > kFrontCountMaxF;
+    if (patch_f32 || counted) e = launch_patch(map->dm, f, i0, counted ? s->patch : nullptr, patch_f32, st);
     if (e == hipSuccess) {
         TrunkArgs a;
         a.m = map->dm;
@@ -84,6 +86,7 @@ int run_trunk(nbt_ig_surrogate* s, const nbt_ig_map* map, const float poi[3], fl
         a.i0x = i0[0];
         a.i0y = i0[1];
         a.i0z = i0[2];
+        a.patch = counted ? s->patch : nullptr;
         for (int l = 0; l < 4; ++l) {
             a.w[l] = s->conv_w[l];
             a.b[l] = s->conv_b[l];
@@ -194,6 +197,7 @@ int nbt_ig_surrogate_create(nbt_ig_ctx* ctx, const void* weights, size_t nbytes,
     if (e == hipSuccess) e = dalloc(s, &s->act2, (size_t)kConvOut[1] * 8 * 8 * 8);
     if (e == hipSuccess) e = dalloc(s, &s->act3, (size_t)kConvOut[2] * 4 * 4 * 4);
     if (e == hipSuccess) e = dalloc(s, &s->feat, kFeat);
+    if (e == hipSuccess) e = dalloc(s, &s->patch, 2 * (size_t)kPatchCells);
     if (e == hipSuccess) e = dalloc(s, &s->c, kHidden);
     if (e == hipSuccess) e = dalloc(s, &s->cand, kMaxRescore);
     if (e == hipSuccess) e = dalloc(s, &s->cand_poses, 12 * (size_t)kMaxRescore);

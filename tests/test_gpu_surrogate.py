@@ -107,6 +107,34 @@ def test_trunk_and_predictions_close_to_reference(nbt, ctx, setup):
         assert np.allclose(p.cpu().numpy(), got[:n], rtol=0, atol=1e-6 * scale)
 
 
+def test_trunk_from_the_counted_patch(nbt, ctx, setup):
+    """Cells of 3 voxels (a 5 m patch on 5 cm voxels, PoI near a corner): the trunk reads the
+    patch counted by its own pass instead of counting in its first launch; its features meet
+    the same bar against the reference, and its patch output is exact."""
+    import torch
+    sc, _, _, _, m = setup
+    _note("surrogate trunk from the counted patch (3-voxel cells)")
+    blob = _blob(704, extent=5.0)
+    params, meta = S.unpack_weights(blob)
+    sur = nbt.Surrogate(ctx, blob)
+    try:
+        for poi in (np.asarray(sc.poi, np.float32), np.array([0.3, 3.0, 0.2], np.float32)):
+            patch, feat = sur.features(m, poi)
+            torch.cuda.synchronize()
+            ref_patch = S.extract_patch(sc.P, sc.voxel, sc.origin, poi, meta["extent"])
+            assert np.array_equal(patch.cpu().numpy(), ref_patch.astype(np.float32))
+            feat_ref = S.trunk(params, ref_patch, emulate_bf16=True)
+            f = feat.cpu().numpy().astype(np.float64)
+            assert np.max(np.abs(f - feat_ref)) <= 2e-2 * max(np.max(np.abs(feat_ref)), 1e-6)
+            assert np.mean(f == feat_ref) > 0.9
+            # the trunk alone (no patch output) gives the same features
+            _, feat2 = sur.features(m, poi, want_patch=False)
+            torch.cuda.synchronize()
+            assert torch.equal(feat2, feat)
+    finally:
+        sur.close()
+
+
 def test_select_is_exact_reranking(nbt, ctx, setup):
     import torch
     sc, poi, blob, sur, m = setup
