@@ -178,14 +178,16 @@ inline uint32_t vp_tiles(const CamParams& c, int tile_w_log2) {
 // tiles_per_wave == 0: as few workgroups as 16 tiles per wave allow, with the
 // tiles dealt evenly over them (no wave of a small camera left idle, no short
 // last workgroup on a large one); when n perspectives (n > 0) would give
-// fewer than 8 workgroups per CU, each perspective is split further (down to
-// one tile per wave) so that small calls still fill the chip.
+// fewer than 64 workgroups per CU, each perspective is split further (down to
+// one tile per wave): small calls then fill the chip, and rays of uneven
+// length (views that hit an object next to views into open space) spread
+// over many short workgroups instead of a few long ones.
 inline VpLaunch resolve_launch(const CamParams& c, VpLaunch L, uint32_t n = 0, int cu_count = 0) {
     if (L.tiles_per_wave > 0) return L;
     const uint32_t tiles = vp_tiles(c, L.tile_w_log2);
     const uint32_t waves = (uint32_t)L.waves;
     uint32_t groups = (tiles + waves * 16 - 1) / (waves * 16);
-    const uint64_t want = 8ull * (uint64_t)(cu_count > 0 ? cu_count : 0);
+    const uint64_t want = 64ull * (uint64_t)(cu_count > 0 ? cu_count : 0);
     if (n > 0 && (uint64_t)n * groups < want) {
         const uint32_t most = (tiles + waves - 1) / waves;
         const uint64_t g = (want + n - 1) / n;
