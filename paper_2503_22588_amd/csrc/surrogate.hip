@@ -70,13 +70,14 @@ __global__ __launch_bounds__(256) void patch_kernel(DevMap m, int f, int i0x, in
 }
 
 // ---------------------------------------------------------------- trunk ----
-// The trunk in four launches.  trunk_front: workgroup b of 64 owns a 2^3 block
-// of the 8^3 conv2 outputs.  It takes the 11^3 patch cells that block depends
-// on (cells outside the 32^3 patch are conv1's zero padding) into LDS as BF16
-// fractions: counted straight from the map, one thread per cell, when cells
-// are at most kFrontCountMaxF voxels wide, else read from the patch that
-// launch_patch counted over the whole chip first (64 workgroups counting
-// 5^3-voxel cells took 74 us; the separate pass spreads them over every CU).
+// The trunk in four launches (after the patch pass for wide cells, below).
+// trunk_front: workgroup b of 64 owns a 2^3 block of the 8^3 conv2 outputs.
+// It takes the 11^3 patch cells that block depends on (cells outside the
+// 32^3 patch are conv1's zero padding) into LDS as BF16 fractions: counted
+// straight from the map, one thread per cell, when cells are at most
+// kFrontCountMaxF voxels wide, else read from the patch that launch_patch
+// counted over the whole chip first (64 workgroups counting 5^3-voxel cells
+// took 74 us; the separate pass spreads them over every CU).
 // It then computes the 5^3 conv1
 // outputs around its block (those outside the 16^3 grid are conv2's zero
 // padding) and its eight conv2 positions, all from LDS, and stores them
