@@ -107,14 +107,16 @@ def test_trunk_and_predictions_close_to_reference(nbt, ctx, setup):
         assert np.allclose(p.cpu().numpy(), got[:n], rtol=0, atol=1e-6 * scale)
 
 
-def test_trunk_from_the_counted_patch(nbt, ctx, setup):
-    """Cells of 3 voxels (a 5 m patch on 5 cm voxels, PoI near a corner): the trunk reads the
-    patch counted by its own pass instead of counting in its first launch; its features meet
-    the same bar against the reference, and its patch output is exact."""
+@pytest.mark.parametrize("extent", [5.0, 8.0], ids=["3-voxel cells", "5-voxel cells"])
+def test_trunk_from_the_counted_patch(nbt, ctx, setup, extent):
+    """Cells of 3 or 5 voxels (a 5 m or 8 m patch on 5 cm voxels; PoI at the map's centre and
+    near a corner, so that cells straddle the map's faces): the trunk reads the patch counted
+    by its own pass instead of counting in its first launch; its features meet the same bar
+    against the reference, and its patch output is exact."""
     import torch
     sc, _, _, _, m = setup
-    _note("surrogate trunk from the counted patch (3-voxel cells)")
-    blob = _blob(704, extent=5.0)
+    _note(f"surrogate trunk from the counted patch (extent {extent} m)")
+    blob = _blob(704, extent=extent)
     params, meta = S.unpack_weights(blob)
     sur = nbt.Surrogate(ctx, blob)
     try:
