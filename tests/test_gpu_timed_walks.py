@@ -86,7 +86,8 @@ def _launch(ctx, waves=4, tw=3, tpw=0, remap=0, depth=8):
 
 
 # shapes: (waves, tile_w_log2, tiles_per_wave, xcd_remap, depth); the first is the default
-SHAPES = [(4, 3, 0, 0, 8), (4, 3, 0, 0, 4), (4, 3, 0, 0, 2), (2, 2, 3, 1, 8), (8, 4, 1, 0, 4), (1, 3, 2, 0, 1)]
+SHAPES = [(4, 3, 0, 0, 8), (4, 3, 0, 0, 4), (4, 3, 0, 0, 2), (2, 2, 3, 1, 8), (8, 4, 1, 0, 4), (1, 3, 2, 0, 1),
+          (1, 3, 4, 0, 8)]
 
 
 def _trace_vp(nbt, m, cam, dposes, want_steps):
@@ -173,9 +174,10 @@ def test_timed_walk_edge_cases(nbt, ctx):
 
 
 def test_cfg2_timed_walk_sampled(nbt, ctx):
-    """Config 2 at its real size (256^3 at 2 cm, 160x120 rays, 3 m) in the launch shape the
-    full 4096-perspective call uses: every ray of 64 seeded perspectives, bit for bit; their
-    IG and step counts also equal the full call's bits."""
+    """Config 2 at its real size (256^3 at 2 cm, 160x120 rays, 3 m) in the launch shapes the
+    full 4096-perspective call uses (the default's and the two the autotuner picks): every
+    ray of 64 seeded perspectives, bit for bit; their IG and step counts also equal the full
+    call's bits."""
     import torch
     w = make_config(2)
     scene, cam, poses = w.maps[0], w.camera, w.poses[0]
@@ -183,22 +185,25 @@ def test_cfg2_timed_walk_sampled(nbt, ctx):
     m = nbt.Map(ctx, scene.P, scene.voxel, scene.origin)
     rng = np.random.default_rng(22588)
     pick = np.sort(rng.choice(poses.shape[0], size=64, replace=False))
-    # 160x120 rays in 8x8 tiles = 300 tiles; 4 waves of 15 tiles per workgroup, 5 workgroups
-    # per perspective: the shape the default launch resolves to for 4096 perspectives
-    _launch(ctx, 4, 3, 15, 0, 8)
-    try:
-        ig_all, st_all = nbt.eval_viewpoints(m, cam, _dev(poses))
-        ig, st, d = _trace_vp(nbt, m, cam, _dev(poses[pick]), True)
-    finally:
-        _launch(ctx)
-    torch.cuda.synchronize()
-    assert np.array_equal(ig.cpu().numpy().view(np.uint32), ig_all.cpu().numpy()[pick].view(np.uint32))
-    assert np.array_equal(st.cpu().numpy(), st_all.cpu().numpy()[pick])
     ref = oracle.trace_rays(scene, cam, poses[pick])
-    _records_equal(d, ref, "cfg2 sample")
     ig_ref, st_ref = oracle.eval_viewpoints(scene, cam, poses[pick])
-    assert np.array_equal(st.cpu().numpy().view(np.uint64), st_ref)
-    assert _ig_rel(ig.cpu().numpy(), ig_ref) <= IG_RTOL
+    # 160x120 rays in 8x8 tiles = 300 tiles; the default resolves to 4 waves of 15 tiles per
+    # workgroup (5 per perspective) for 4096 perspectives; the tuner picks single waves of 4
+    # or 2 tiles (75 or 150 per perspective)
+    for shape in ((4, 3, 15, 0, 8), (1, 3, 4, 0, 8), (1, 3, 2, 0, 8)):
+        _note(f"cfg2 timed walk, shape {shape}")
+        _launch(ctx, *shape)
+        try:
+            ig_all, st_all = nbt.eval_viewpoints(m, cam, _dev(poses))
+            ig, st, d = _trace_vp(nbt, m, cam, _dev(poses[pick]), True)
+        finally:
+            _launch(ctx)
+        torch.cuda.synchronize()
+        assert np.array_equal(ig.cpu().numpy().view(np.uint32), ig_all.cpu().numpy()[pick].view(np.uint32))
+        assert np.array_equal(st.cpu().numpy(), st_all.cpu().numpy()[pick])
+        _records_equal(d, ref, f"cfg2 sample {shape}")
+        assert np.array_equal(st.cpu().numpy().view(np.uint64), st_ref)
+        assert _ig_rel(ig.cpu().numpy(), ig_ref) <= IG_RTOL
     m.close()
 
 
